@@ -1,0 +1,148 @@
+/*
+ * kfmeg.h -- C ABI of the MI355X (gfx950) Kalman filter / fixed-interval
+ * smoother for the dynamic MEG inverse problem (Long, Purdon, Temereanca,
+ * Desai, Hamalainen, Brown, Ann. Appl. Stat. 5(2B), 2011).
+ *
+ * Model (Section 2, eqn1 and eqn3 with F = I, the random walk):
+ *     x_t = x_{t-1} + w_t,   w_t ~ N(0, Q)          (Sigma_w in the paper)
+ *     y_t = X x_t + v_t,     v_t ~ N(0, R)          (H and Sigma_epsilon)
+ * with x_0 ~ N(x0, P0). N is the state dimension (sources, or 3 x sites for
+ * free orientation), m the number of sensors, T the number of time steps.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers to float64 data, row-major and
+ *    contiguous (leading dimension = number of columns), unless stated.
+ *  - The caller owns every buffer it passes; kf_create copies its inputs into
+ *    plan-owned storage, so they may be freed after it returns. Y and output
+ *    buffers must stay valid for the duration of the call.
+ *  - Work is enqueued on the plan's stream (a hipStream_t passed as void*,
+ *    NULL = the null stream) and every call synchronises that stream before it
+ *    returns, so the returned status is final.
+ *  - Argument errors are reported before any launch. Nothing throws or
+ *    aborts across this boundary; kf_last_error() gives a message.
+ *  - A plan is used by one host thread at a time; distinct plans may run
+ *    concurrently on distinct streams.
+ */
+#ifndef KFMEG_H
+#define KFMEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kf_plan kf_plan;
+
+typedef enum {
+    KF_OK = 0,
+    KF_EINVAL = 1,   /* bad argument (shape, null pointer, non-finite data) */
+    KF_ENOTPD = 2,   /* S or P_{t+1|t} not positive definite (step and matrix in the message) */
+    KF_ENOMEM = 3,   /* device allocation failed or the HBM budget is too small */
+    KF_EHIP = 4,     /* a HIP runtime call failed */
+    KF_ESTATE = 5    /* call out of order (kf_smooth before a completed kf_filter) */
+} kf_status;
+
+typedef enum {
+    KF_FP64 = 0,     /* every product and factorisation in float64 */
+    KF_MIXED = 1     /* N x N products on FP32 MFMA (FP32 accumulate); Cholesky of S and of
+                        P_{t+1|t}, the smoother gain and all epilogues in float64 */
+} kf_precision;
+
+typedef struct {
+    int precision;            /* kf_precision */
+    int store_fp32;           /* store the filtered covariances P_{t|t} in float32 */
+    size_t hbm_budget_bytes;  /* cap on the covariance store; 0 = whatever is free */
+    int checkpoint_stride;    /* keep every k-th P_{t|t} and recompute the rest in the
+                                 backward pass; 0 = automatic (only if the store does not fit) */
+} kf_options;
+
+/* Defaults: KF_FP64, float64 store, no budget cap, automatic checkpointing. */
+void kf_default_options(kf_options* opt);
+
+/*
+ * kf_create: allocate a plan for state dimension N, m sensors and up to T_max
+ * steps, and copy the model into it.
+ *   X  (m x N) lead field, Q (N x N) and P0 (N x N) symmetric positive
+ *   (semi)definite, R (m x m) symmetric positive definite, x0 (N).
+ * The inputs define eqn1, eqn3 and the initial condition that follows eqn10
+ * (x0 and P0 are inputs rather than the paper's MNE-based choice).
+ * Returns KF_EINVAL for non-positive sizes or null pointers, KF_ENOMEM if the
+ * workspaces do not fit. *out is NULL on failure.
+ */
+kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max,
+                    const double* X, const double* Q, const double* R,
+                    const double* x0, const double* P0,
+                    const kf_options* opt, void* stream);
+
+/*
+ * kf_filter: the Kalman filter, eqn6-eqn10 and the covariance update that
+ * follows eqn10, for t = 1..T (1 <= T <= T_max), starting from x0, P0.
+ *   Y          (T x m) data, row t-1 = y_t
+ *   x_filt     (T x N) out: x_{t|t}
+ *   Pdiag_filt (T x N) out, or NULL: diagonals of P_{t|t}
+ * The filtered covariances stay in the plan for kf_smooth. Returns KF_ENOTPD
+ * (with the step in kf_last_error) if S_t = X P_{t|t-1} X^T + R is not
+ * positive definite, KF_EINVAL if Y holds a non-finite value.
+ */
+kf_status kf_filter(kf_plan* plan, int64_t T, const double* Y,
+                    double* x_filt, double* Pdiag_filt);
+
+/*
+ * kf_smooth: the fixed-interval smoother eqn11-eqn13 (standard
+ * Rauch-Tung-Striebel form; the printed eqn12/eqn13 carry misprints) for
+ * t = T-1..1 from the last kf_filter call, initialised with x_{T|T}, P_{T|T}.
+ *   x_smooth     (T x N) out: x_{t|T}
+ *   Pdiag_smooth (T x N) out, or NULL: diagonals of P_{t|T}
+ *   P_smooth     (T x N x N) out, or NULL: every P_{t|T} (small sizes only)
+ * Returns KF_ESTATE without a completed kf_filter, KF_ENOTPD if
+ * P_{t+1|t} = P_{t|t} + Q is not positive definite.
+ */
+kf_status kf_smooth(kf_plan* plan, double* x_smooth, double* Pdiag_smooth,
+                    double* P_smooth);
+
+/* Copy the stored filtered covariance P_{t|t} (1 <= t <= T) into P_out (N x N, device). */
+kf_status kf_get_filtered_cov(kf_plan* plan, int64_t t, double* P_out);
+
+/*
+ * mne_solve: the minimum-norm estimate of eqn5 for every column of the data,
+ *   J_t = C X^T (X C X^T + R)^{-1} y_t,   t = 1..T,
+ * with C (N x N) the symmetric positive definite source prior (lambda R in
+ * eqn5; any SPD matrix is accepted), R (m x m) the sensor noise covariance.
+ *   Y (T x m) in, J (T x N) out.
+ * Stateless: allocates its own workspace, synchronises `stream` before it
+ * returns. KF_ENOTPD if X C X^T + R is not positive definite.
+ */
+kf_status mne_solve(int64_t N, int64_t m, int64_t T, const double* X, const double* C,
+                    const double* R, const double* Y, double* J, void* stream);
+
+/* Free a plan and everything it owns. NULL is accepted. */
+void kf_destroy(kf_plan* plan);
+
+/* Message for the last failed call on this plan (or of mne_solve if plan is NULL). */
+const char* kf_last_error(const kf_plan* plan);
+
+/*
+ * Profiling of the smoother's N x N x N products (the triangular products
+ * that form A_t, eqn11, and the two products of eqn13), which carry most of
+ * the arithmetic. With profiling on, kf_smooth brackets each such launch with
+ * a pair of HIP events on the plan's stream; kf_get_profile returns the summed
+ * kernel time in ms, the summed algorithmic flops (N^3 for each triangular or
+ * half-output product, 2 N^3 for the full one) and the number of launches
+ * since profiling was last switched on. kf_set_profiling resets the totals.
+ */
+kf_status kf_set_profiling(kf_plan* plan, int on);
+kf_status kf_get_profile(const kf_plan* plan, double* kernel_ms, double* kernel_flops, int64_t* launches);
+
+/*
+ * Device bytes a plan of this shape would allocate: workspaces plus the full
+ * covariance store for T steps under `opt` (used for admission decisions).
+ */
+size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KFMEG_H */

@@ -1,0 +1,52 @@
+// Kernel-level test entry points (include/kfmeg_debug.h).
+#include "kf_internal.h"
+#include "../../include/kfmeg_debug.h"
+
+using namespace kfmeg;
+
+extern "C" {
+
+int kfd_gemm(int dtype, int M, int N, int K, int flags, const void* A, int64_t lda, const void* B, int64_t ldb,
+             double alpha, double beta, const double* Cin, int64_t ldcin, double* C, int64_t ldc, int ksplit,
+             void* stream) {
+    if (M < 0 || N < 0 || K < 0 || !A || !B || !C || (dtype != 0 && dtype != 1) || ksplit < 1 || (flags & ~127))
+        return 1;
+    if ((flags & G_LOWER) && M != N) return 1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GemmProblem g;
+    g.M = M; g.N = N; g.K = K; g.flags = flags;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb;
+    g.alpha = alpha; g.beta = beta; g.Cin = Cin; g.ldcin = ldcin;
+    g.C = C; g.ldc = ldc;
+    void* part = nullptr;
+    if (ksplit > 1) {
+        if (hipMalloc(&part, (size_t)ksplit * M * N * (dtype == 0 ? 8 : 4)) != hipSuccess) return 4;
+        g.ksplit = ksplit;
+        g.partial = part;
+    }
+    hipError_t e = gemm1(dtype == 0 ? Dt::F64 : Dt::F32, g, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (part) (void)hipFree(part);
+    return e == hipSuccess ? 0 : 4;
+}
+
+int kfd_chol_inv(int n, double* W, int64_t ldw, double* Z, int64_t ldz, int* pivot_row, void* stream) {
+    if (n <= 0 || !W || !Z || ldw < n || ldz < n) return 1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int* dst = nullptr;
+    if (hipMalloc(&dst, 4 * sizeof(int)) != hipSuccess) return 4;
+    int h[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemsetAsync(dst, 0, 4 * sizeof(int), s);
+    if (e == hipSuccess) e = chol_inv(W, ldw, Z, ldz, n, dst, W_MNE, 0, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, dst, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dst);
+    if (e != hipSuccess) return 4;
+    if (h[0]) {
+        if (pivot_row) *pivot_row = h[3];
+        return 2;
+    }
+    return 0;
+}
+
+}  // extern "C"

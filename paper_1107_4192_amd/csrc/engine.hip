@@ -1,0 +1,780 @@
+// Plan, filter, smoother and MNE entry points (the C ABI of include/kfmeg.h).
+//
+// Filter step t (eqn6-eqn10 and the covariance update after eqn10), with
+// P_prev = P_{t-1|t-1}:
+//   B   = X (P_prev + Q)                 m x N   MFMA GEMM, split-K, P + Q fused into the B loads
+//   S   = B X^T + R                      m x m   MFMA GEMM, split-K (fixed-order reduction)
+//   L Li = chol(S)                        m x m   blocked Cholesky fused with L^{-1}
+//   C   = Li B                           m x N   triangular MFMA product (K range trimmed)
+//   x  += C^T (Li (y_t - X x))                   three wave-reduction kernels
+//   P_t = P_prev + Q - C^T C             N x N   lower tiles only, mirrored store (exact symmetry),
+//                                                diagonal out, written straight into store slot t
+// since K = P_pred X^T S^{-1} = C^T Li and K X P_pred = C^T C.
+//
+// Smoother step t (eqn11-eqn13, RTS reading), P_t = P_{t|t}, Pn = P_t + Q = P_{t+1|t}:
+//   L Li = chol(Pn)                      N x N   blocked Cholesky fused with L^{-1}
+//   G   = Li P_t ;  A_t = G^T Li         N x N   two triangular MFMA products: A_t = P_t Pn^{-1}
+//   x_{t|T} = x_{t|t} + A_t (x_{t+1|T} - x_{t|t})
+//   M   = A_t (P_{t+1|T} - P_t - Q)      N x N   MFMA GEMM, difference fused into the B loads
+//   P_{t|T} = P_t + M A_t^T              N x N   lower tiles + mirror, diagonal out
+//
+// Mixed precision runs the N x N products that involve no factor (X P, the
+// downdate C^T C, M and M A^T) on FP32 MFMA with FP32 accumulation, keeps the
+// Cholesky of S and of P_{t+1|t}, the gain A_t and every epilogue in FP64, and
+// may store P_{t|t} in FP32.
+#include "kf_internal.h"
+#include "../../include/kfmeg.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace kfmeg;
+
+struct kf_plan {
+    int64_t N = 0, m = 0, Tmax = 0;
+    kf_options opt{};
+    hipStream_t stream = nullptr;
+    int64_t ldN = 0, ldm = 0;
+    std::vector<void*> allocs;
+
+    // model
+    double *X = nullptr, *Q = nullptr, *R = nullptr, *x0 = nullptr, *P0 = nullptr;
+    float *X32 = nullptr, *Q32 = nullptr, *P032 = nullptr;
+    // filter workspace
+    double *Bm = nullptr, *Cm = nullptr, *S = nullptr, *Lis = nullptr, *e = nullptr, *w = nullptr, *xw = nullptr;
+    float* Cm32 = nullptr;
+    double* partial = nullptr;
+    size_t partial_elems = 0;
+    double* Pw[2] = {nullptr, nullptr};     // float64 working pair (store in float32 or checkpointed)
+    float* P32w = nullptr;                  // float32 copy of P_{t|t} (mixed, float64 store)
+    // covariance store
+    bool store32 = false;
+    int stride = 1;                         // keep slots t with (t+1) % stride == 0 and t = T-1
+    void* store = nullptr;
+    int64_t nslots = 0;
+    // segment buffer for recomputation (checkpointed mode)
+    void* seg = nullptr;
+    // smoother workspace
+    double *W = nullptr, *Li = nullptr, *Ab = nullptr, *Ps[2] = {nullptr, nullptr}, *Pt64 = nullptr;
+    float *A32 = nullptr, *D32 = nullptr, *M32 = nullptr;
+    // status
+    int* dstatus = nullptr;
+    int* hstatus = nullptr;
+    int64_t T_done = 0;
+    double* xf_last = nullptr;    // caller's x_filt of the last kf_filter call (for kf_smooth)
+    std::string err;
+    // profiling of the smoother's N x N x N products (event pairs around each launch)
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<double> ev_flops;
+    size_t ev_used = 0;
+    double prof_ms = 0.0, prof_flops = 0.0;
+    int64_t prof_launches = 0;
+};
+
+namespace {
+
+std::string g_err;
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+struct Fail {
+    kf_status st;
+};
+
+#define HIPCK(expr)                                                                      \
+    do {                                                                                 \
+        hipError_t _e = (expr);                                                          \
+        if (_e != hipSuccess) {                                                          \
+            p->err = std::string(#expr) + ": " + hipGetErrorString(_e);                  \
+            return KF_EHIP;                                                              \
+        }                                                                                \
+    } while (0)
+
+bool mixed(const kf_plan* p) { return p->opt.precision == KF_MIXED; }
+
+template <typename T>
+kf_status alloc(kf_plan* p, T** out, size_t elems) {
+    void* ptr = nullptr;
+    if (elems == 0) elems = 1;
+    hipError_t e = hipMalloc(&ptr, elems * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p->err = "device allocation of " + std::to_string(elems * sizeof(T)) + " bytes failed";
+        return KF_ENOMEM;
+    }
+    p->allocs.push_back(ptr);
+    *out = static_cast<T*>(ptr);
+    return KF_OK;
+}
+
+#define TRY(expr)                           \
+    do {                                    \
+        kf_status _s = (expr);              \
+        if (_s != KF_OK) return _s;         \
+    } while (0)
+
+size_t slot_elems(const kf_plan* p) { return (size_t)p->N * p->ldN; }
+
+void* slot_ptr(const kf_plan* p, int64_t idx) {
+    const size_t esz = p->store32 ? 4 : 8;
+    return static_cast<char*>(p->store) + (size_t)idx * slot_elems(p) * esz;
+}
+
+// Is filtered covariance t (0-based) kept in the store?  Which slot holds it?
+bool kept(const kf_plan* p, int64_t t, int64_t T) { return p->stride == 1 || (t + 1) % p->stride == 0 || t == T - 1; }
+int64_t slot_of(const kf_plan* p, int64_t t, int64_t T) {
+    if (p->stride == 1) return t;
+    if (t == T - 1) return (T - 1) / p->stride;   // after the last full checkpoint
+    return (t + 1) / p->stride - 1;
+}
+int64_t slots_needed(int64_t T, int stride) { return stride == 1 ? T : T / stride + 1; }
+
+size_t store_bytes(int64_t N, int64_t ldN, int64_t T, bool s32, int stride) {
+    return (size_t)slots_needed(T, stride) * (size_t)N * ldN * (s32 ? 4 : 8);
+}
+
+size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride) {
+    const int64_t ldN = round_up(N, 16), ldm = round_up(m, 16);
+    const size_t NN = (size_t)N * ldN;
+    size_t b = 0;
+    b += 8 * (2 * NN + (size_t)m * ldN + (size_t)m * ldm + 2 * (size_t)N);   // Q, P0, X, R, x0
+    b += 8 * (2 * (size_t)m * ldN + 2 * (size_t)m * ldm + 3 * (size_t)N + 64);
+    b += 8 * (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);                 // split-K partials
+    b += 8 * 5 * NN;                                                             // W, Li, A, Ps x2
+    if (mix) b += 4 * (3 * NN + (size_t)m * ldN + (size_t)m * ldN + NN) + 8 * NN;
+    if (s32 || stride > 1) b += 8 * 2 * NN;
+    if (mix) b += 4 * NN;
+    if (stride > 1) b += (size_t)stride * NN * (s32 ? 4 : 8);
+    return b;
+}
+
+kf_status status_check(kf_plan* p, const char* phase) {
+    if (p->hstatus[0]) {
+        const char* which = p->hstatus[1] == W_S ? "S_t = X P_{t|t-1} X^T + R"
+                          : p->hstatus[1] == W_PPRED ? "P_{t+1|t} = P_{t|t} + Q" : "X C X^T + R";
+        char buf[256];
+        snprintf(buf, sizeof buf, "%s: %s is not positive definite at step t=%d (pivot row %d)", phase, which,
+                 p->hstatus[2], p->hstatus[3]);
+        p->err = buf;
+        return KF_ENOTPD;
+    }
+    return KF_OK;
+}
+
+// One covariance step of the filter from P_prev (index t-1, or P0) to P_t; with `x`/`y`, also the mean.
+// Pprev64/32: float64 / float32 views of P_{t-1|t-1} (the float32 one only in mixed mode).
+kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, const float* Pprev32, double* Pout64,
+                          float* Pout32, double* diag_out, const double* y, double* x_out_row) {
+    const int N = (int)p->N, m = (int)p->m;
+    hipStream_t s = p->stream;
+    // B = X (P_prev + Q)
+    {
+        GemmProblem g;
+        g.M = m; g.N = N; g.K = N;
+        g.ksplit = 4;
+        g.partial = p->partial;
+        g.C = p->Bm; g.ldc = p->ldN;
+        if (mixed(p)) {
+            g.A = p->X32; g.lda = p->ldN;
+            g.B = Pprev32; g.ldb = p->ldN; g.B2 = p->Q32; g.ldb2 = p->ldN; g.b2coef = 1.0;
+            HIPCK(gemm1(Dt::F32, g, s));
+        } else {
+            g.A = p->X; g.lda = p->ldN;
+            g.B = Pprev64; g.ldb = p->ldN; g.B2 = p->Q; g.ldb2 = p->ldN; g.b2coef = 1.0;
+            HIPCK(gemm1(Dt::F64, g, s));
+        }
+    }
+    // S = B X^T + R
+    {
+        GemmProblem g;
+        g.M = m; g.N = m; g.K = N;
+        g.A = p->Bm; g.lda = p->ldN;
+        g.B = p->X; g.ldb = p->ldN; g.flags = G_TB;
+        g.Cin = p->R; g.ldcin = p->ldm; g.beta = 1.0;
+        g.C = p->S; g.ldc = p->ldm;
+        g.ksplit = std::max(1, std::min(32, N / 128));
+        g.partial = p->partial;
+        HIPCK(gemm1(Dt::F64, g, s));
+    }
+    HIPCK(chol_inv(p->S, p->ldm, p->Lis, p->ldm, m, p->dstatus, W_S, (int)t + 1, s));
+    // C = Li B
+    {
+        GemmProblem g;
+        g.M = m; g.N = N; g.K = m;
+        g.A = p->Lis; g.lda = p->ldm; g.flags = G_ALOWER;
+        g.B = p->Bm; g.ldb = p->ldN;
+        g.C = p->Cm; g.ldc = p->ldN;
+        if (mixed(p)) { g.C32 = p->Cm32; g.ldc32 = p->ldN; }
+        HIPCK(gemm1(Dt::F64, g, s));
+    }
+    if (y) {
+        HIPCK(resid(p->X, p->ldN, p->xw, y, p->e, m, N, s));
+        HIPCK(trmv_lower(p->Lis, p->ldm, p->e, p->w, m, s));
+        HIPCK(gemv_t_add(p->Cm, p->ldN, p->w, p->xw, p->xw, x_out_row, m, N, s));
+    }
+    // P_t = P_prev + Q - C^T C
+    {
+        GemmProblem g;
+        g.M = N; g.N = N; g.K = m;
+        g.flags = G_TA | G_LOWER | G_MIRROR;
+        g.alpha = -1.0;
+        g.Cin = Pprev64; g.ldcin = p->ldN; g.beta = 1.0;
+        g.Cin2 = p->Q; g.ldcin2 = p->ldN; g.gamma = 1.0;
+        g.C = Pout64; g.ldc = p->ldN;
+        g.C32 = Pout32; g.ldc32 = p->ldN;
+        g.diag = diag_out;
+        if (mixed(p)) {
+            g.A = p->Cm32; g.lda = p->ldN; g.B = p->Cm32; g.ldb = p->ldN;
+            HIPCK(gemm1(Dt::F32, g, s));
+        } else {
+            g.A = p->Cm; g.lda = p->ldN; g.B = p->Cm; g.ldb = p->ldN;
+            HIPCK(gemm1(Dt::F64, g, s));
+        }
+    }
+    return KF_OK;
+}
+
+kf_status sync_and_check(kf_plan* p, const char* phase) {
+    HIPCK(hipMemcpyAsync(p->hstatus, p->dstatus, 4 * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+    HIPCK(hipStreamSynchronize(p->stream));
+    return status_check(p, phase);
+}
+
+// Launch one of the smoother's N x N x N products (named instantiation), timed when profiling.
+kf_status big_gemm(kf_plan* p, Dt dt, GemmProblem g, double flops) {
+    g.flags |= G_NXN;
+    if (p->prof) {
+        while (p->ev.size() < p->ev_used + 2) {
+            hipEvent_t e;
+            HIPCK(hipEventCreate(&e));
+            p->ev.push_back(e);
+        }
+        HIPCK(hipEventRecord(p->ev[p->ev_used], p->stream));
+    }
+    HIPCK(gemm1(dt, g, p->stream));
+    if (p->prof) {
+        HIPCK(hipEventRecord(p->ev[p->ev_used + 1], p->stream));
+        p->ev_flops.push_back(flops);
+        p->ev_used += 2;
+    }
+    return KF_OK;
+}
+
+// After the stream has been synchronised: fold the recorded event pairs into the totals.
+kf_status collect_profile(kf_plan* p) {
+    for (size_t k = 0; k + 1 < p->ev_used; k += 2) {
+        float ms = 0.f;
+        HIPCK(hipEventElapsedTime(&ms, p->ev[k], p->ev[k + 1]));
+        p->prof_ms += ms;
+        p->prof_flops += p->ev_flops[k / 2];
+        p->prof_launches += 1;
+    }
+    p->ev_used = 0;
+    p->ev_flops.clear();
+    return KF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void kf_default_options(kf_options* opt) {
+    if (!opt) return;
+    opt->precision = KF_FP64;
+    opt->store_fp32 = 0;
+    opt->hbm_budget_bytes = 0;
+    opt->checkpoint_stride = 0;
+}
+
+size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt) {
+    kf_options o;
+    kf_default_options(&o);
+    if (opt) o = *opt;
+    if (N <= 0 || m <= 0 || T <= 0) return 0;
+    const int64_t ldN = round_up(N, 16);
+    const int stride = o.checkpoint_stride > 0 ? o.checkpoint_stride : 1;
+    return workspace_bytes(N, m, o.precision == KF_MIXED, o.store_fp32, stride) +
+           store_bytes(N, ldN, T, o.store_fp32, stride);
+}
+
+kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const double* X, const double* Q,
+                    const double* R, const double* x0, const double* P0, const kf_options* opt, void* stream) {
+    if (!out) return KF_EINVAL;
+    *out = nullptr;
+    if (N <= 0 || m <= 0 || T_max <= 0 || N > (1 << 20) || m > (1 << 16)) {
+        g_err = "kf_create: sizes must be positive (N <= 2^20, m <= 2^16)";
+        return KF_EINVAL;
+    }
+    if (!X || !Q || !R || !x0 || !P0) {
+        g_err = "kf_create: null model pointer";
+        return KF_EINVAL;
+    }
+    kf_plan* p = new kf_plan();
+    p->N = N; p->m = m; p->Tmax = T_max;
+    kf_default_options(&p->opt);
+    if (opt) p->opt = *opt;
+    if (p->opt.precision != KF_FP64 && p->opt.precision != KF_MIXED) {
+        g_err = "kf_create: unknown precision";
+        delete p;
+        return KF_EINVAL;
+    }
+    p->stream = static_cast<hipStream_t>(stream);
+    p->ldN = round_up(N, 16);
+    p->ldm = round_up(m, 16);
+    p->store32 = p->opt.store_fp32 != 0;
+
+    // Store layout: all T_max slots, or every k-th slot when over budget.
+    size_t budget = p->opt.hbm_budget_bytes;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) budget = fr > ((size_t)1 << 30) ? fr - ((size_t)1 << 30) : 0;
+    }
+    int stride = p->opt.checkpoint_stride > 0 ? p->opt.checkpoint_stride : 1;
+    const bool mix = mixed(p);
+    if (p->opt.checkpoint_stride <= 0) {
+        while (stride < T_max &&
+               workspace_bytes(N, m, mix, p->store32, stride) + store_bytes(N, p->ldN, T_max, p->store32, stride) >
+                   budget) {
+            stride = stride == 1 ? std::max<int>(2, (int)std::ceil(std::sqrt((double)T_max))) : stride + 1;
+        }
+    }
+    if (workspace_bytes(N, m, mix, p->store32, stride) + store_bytes(N, p->ldN, T_max, p->store32, stride) >
+        budget) {
+        g_err = "kf_create: the covariance store does not fit the HBM budget even with checkpointing";
+        delete p;
+        return KF_ENOMEM;
+    }
+    p->stride = stride;
+    p->nslots = slots_needed(T_max, stride);
+
+    kf_status st = KF_OK;
+    auto fail = [&](kf_status s) {
+        g_err = p->err;
+        kf_destroy(p);
+        return s;
+    };
+    const size_t NN = slot_elems(p);
+    const size_t mN = (size_t)m * p->ldN, mm = (size_t)m * p->ldm;
+#define ALLOC(ptr, n)                        \
+    if ((st = alloc(p, &(ptr), (n))) != KF_OK) return fail(st);
+    ALLOC(p->X, mN); ALLOC(p->Q, NN); ALLOC(p->R, mm); ALLOC(p->x0, (size_t)N); ALLOC(p->P0, NN);
+    ALLOC(p->Bm, mN); ALLOC(p->Cm, mN); ALLOC(p->S, mm); ALLOC(p->Lis, mm);
+    ALLOC(p->e, (size_t)m); ALLOC(p->w, (size_t)m); ALLOC(p->xw, (size_t)N);
+    p->partial_elems = (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);
+    ALLOC(p->partial, p->partial_elems);
+    ALLOC(p->dstatus, 4);
+    ALLOC(p->W, NN); ALLOC(p->Li, NN); ALLOC(p->Ab, NN); ALLOC(p->Ps[0], NN); ALLOC(p->Ps[1], NN);
+    if (mix) {
+        ALLOC(p->X32, mN); ALLOC(p->Q32, NN); ALLOC(p->P032, NN); ALLOC(p->Cm32, mN);
+        ALLOC(p->A32, NN); ALLOC(p->D32, NN); ALLOC(p->M32, NN); ALLOC(p->Pt64, NN);
+        ALLOC(p->P32w, NN);
+    }
+    if (p->store32 || stride > 1) { ALLOC(p->Pw[0], NN); ALLOC(p->Pw[1], NN); }
+    {
+        void* sp = nullptr;
+        const size_t bytes = (size_t)p->nslots * NN * (p->store32 ? 4 : 8);
+        if (hipMalloc(&sp, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p->err = "device allocation of the covariance store (" + std::to_string(bytes) + " bytes) failed";
+            return fail(KF_ENOMEM);
+        }
+        p->allocs.push_back(sp);
+        p->store = sp;
+        if (stride > 1) {
+            if (hipMalloc(&sp, (size_t)stride * NN * (p->store32 ? 4 : 8)) != hipSuccess) {
+                (void)hipGetLastError();
+                p->err = "device allocation of the recompute segment failed";
+                return fail(KF_ENOMEM);
+            }
+            p->allocs.push_back(sp);
+            p->seg = sp;
+        }
+    }
+#undef ALLOC
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->hstatus), 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        p->err = "pinned host allocation failed";
+        return fail(KF_ENOMEM);
+    }
+    hipStream_t s = p->stream;
+    auto cp = [&](void* dst, bool d32, int64_t ldd, const double* src, int64_t rows, int64_t cols) {
+        return copy2d((int)rows, (int)cols, dst, d32, ldd, src, false, cols, s);
+    };
+    if (cp(p->X, false, p->ldN, X, m, N) != hipSuccess || cp(p->Q, false, p->ldN, Q, N, N) != hipSuccess ||
+        cp(p->R, false, p->ldm, R, m, m) != hipSuccess || cp(p->x0, false, N, x0, 1, N) != hipSuccess ||
+        cp(p->P0, false, p->ldN, P0, N, N) != hipSuccess) {
+        p->err = "kf_create: copying the model failed";
+        return fail(KF_EHIP);
+    }
+    if (mix) {
+        if (cp(p->X32, true, p->ldN, X, m, N) != hipSuccess || cp(p->Q32, true, p->ldN, Q, N, N) != hipSuccess ||
+            cp(p->P032, true, p->ldN, P0, N, N) != hipSuccess) {
+            p->err = "kf_create: copying the model failed";
+            return fail(KF_EHIP);
+        }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        p->err = "kf_create: stream synchronisation failed";
+        return fail(KF_EHIP);
+    }
+    *out = p;
+    return KF_OK;
+}
+
+static kf_status filter_impl(kf_plan* p, int64_t T, const double* Y, double* x_filt, double* Pdiag) {
+    hipStream_t s = p->stream;
+    const int64_t N = p->N, m = p->m;
+    HIPCK(hipMemsetAsync(p->dstatus, 0, 4 * sizeof(int), s));
+    HIPCK(nonfinite_scan(Y, T * m, p->dstatus, s));
+    HIPCK(hipMemcpyAsync(p->hstatus, p->dstatus, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    if (p->hstatus[0]) {
+        p->err = "kf_filter: Y holds a non-finite value";
+        return KF_EINVAL;
+    }
+    HIPCK(hipMemcpyAsync(p->xw, p->x0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const bool direct = !p->store32 && p->stride == 1;   // store slot t is the working P
+    const double* prev64 = p->P0;
+    const float* prev32 = p->P032;
+    for (int64_t t = 0; t < T; ++t) {
+        double* out64 = direct ? static_cast<double*>(slot_ptr(p, t)) : p->Pw[t & 1];
+        float* out32 = nullptr;
+        if (p->store32 && kept(p, t, T)) out32 = static_cast<float*>(slot_ptr(p, slot_of(p, t, T)));
+        else if (mixed(p)) out32 = p->P32w;     // float32 operand of the next step's product
+        TRY(filter_cov_step(p, t, prev64, prev32, out64, out32, Pdiag ? Pdiag + t * N : nullptr, Y + t * m,
+                            x_filt + t * N));
+        if (!direct && !p->store32 && kept(p, t, T)) {
+            HIPCK(hipMemcpyAsync(slot_ptr(p, slot_of(p, t, T)), out64, slot_elems(p) * 8, hipMemcpyDeviceToDevice,
+                                 s));
+        }
+        prev64 = out64;
+        prev32 = out32;
+    }
+    return sync_and_check(p, "kf_filter");
+}
+
+kf_status kf_filter(kf_plan* p, int64_t T, const double* Y, double* x_filt, double* Pdiag_filt) {
+    if (!p) return KF_EINVAL;
+    p->err.clear();
+    p->T_done = 0;
+    if (T <= 0 || T > p->Tmax || !Y || !x_filt) {
+        p->err = "kf_filter: need 1 <= T <= T_max and non-null Y, x_filt";
+        return KF_EINVAL;
+    }
+    kf_status st = filter_impl(p, T, Y, x_filt, Pdiag_filt);
+    if (st == KF_OK) {
+        p->T_done = T;
+        p->xf_last = x_filt;
+    }
+    return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Recompute the filtered covariances of steps [t0, t1] (0-based) from the checkpoint before t0 into
+// the segment buffer; seg slot (t - t0) holds P_t afterwards.
+kf_status recompute_segment(kf_plan* p, int64_t t0, int64_t t1, int64_t T) {
+    hipStream_t s = p->stream;
+    const bool s32 = p->store32;
+    const size_t esz = s32 ? 4 : 8;
+    // starting covariance: P_{t0-1} from its checkpoint (or P0)
+    const double* prev64;
+    const float* prev32 = nullptr;
+    if (t0 == 0) {
+        prev64 = p->P0;
+        prev32 = p->P032;
+    } else {
+        const void* src = slot_ptr(p, slot_of(p, t0 - 1, T));
+        HIPCK(copy2d((int)p->N, (int)p->N, p->Pw[0], false, p->ldN, src, s32, p->ldN, s));
+        prev64 = p->Pw[0];
+        if (mixed(p)) {
+            if (s32) prev32 = static_cast<const float*>(src);
+            else {
+                HIPCK(copy2d((int)p->N, (int)p->N, p->P32w, true, p->ldN, src, false, p->ldN, s));
+                prev32 = p->P32w;
+            }
+        }
+    }
+    for (int64_t t = t0; t <= t1; ++t) {
+        double* out64 = p->Pw[(t - t0 + 1) & 1];
+        void* segslot = static_cast<char*>(p->seg) + (size_t)(t - t0) * slot_elems(p) * esz;
+        float* out32 = s32 ? static_cast<float*>(segslot) : (mixed(p) ? p->P32w : nullptr);
+        TRY(filter_cov_step(p, t, prev64, prev32, out64, out32, nullptr, nullptr, nullptr));
+        if (!s32) HIPCK(hipMemcpyAsync(segslot, out64, slot_elems(p) * 8, hipMemcpyDeviceToDevice, s));
+        prev64 = out64;
+        prev32 = out32;
+    }
+    return KF_OK;
+}
+
+// One smoother step t (0-based, t <= T-2). Pt: stored P_{t|t} (float32 or float64).
+kf_status smooth_step(kf_plan* p, int64_t t, const void* Pt, const double* Ps_next, double* Ps_out,
+                      const double* xf, double* xs, double* Pdiag) {
+    hipStream_t s = p->stream;
+    const int N = (int)p->N;
+    const int64_t ld = p->ldN;
+    const bool s32 = p->store32;
+    const double* Pt64 = static_cast<const double*>(Pt);
+    if (s32 || mixed(p)) {
+        if (s32) {
+            HIPCK(copy2d(N, N, p->Pt64 ? p->Pt64 : p->Pw[0], false, ld, Pt, true, ld, s));
+            Pt64 = p->Pt64 ? p->Pt64 : p->Pw[0];
+        }
+    }
+    // W = P_t + Q  (= P_{t+1|t}, eqn7)
+    HIPCK(axpby3(N, N, p->W, false, ld, Pt64, false, ld, p->Q, false, ld, 1.0, nullptr, false, 0, 0.0, s));
+    HIPCK(chol_inv(p->W, ld, p->Li, ld, N, p->dstatus, W_PPRED, (int)t + 1, s));
+    // G = Li P_t  (into W; L is not needed any more)
+    {
+        GemmProblem g;
+        g.M = N; g.N = N; g.K = N;
+        g.A = p->Li; g.lda = ld; g.flags = G_ALOWER;
+        g.B = Pt64; g.ldb = ld;
+        g.C = p->W; g.ldc = ld;
+        TRY(big_gemm(p, Dt::F64, g, (double)N * N * N));
+    }
+    // A_t = G^T Li  (eqn11)
+    {
+        GemmProblem g;
+        g.M = N; g.N = N; g.K = N;
+        g.A = p->W; g.lda = ld; g.flags = G_TA | G_BLOWER;
+        g.B = p->Li; g.ldb = ld;
+        g.C = p->Ab; g.ldc = ld;
+        if (mixed(p)) { g.C32 = p->A32; g.ldc32 = ld; }
+        TRY(big_gemm(p, Dt::F64, g, (double)N * N * N));
+    }
+    // x_{t|T} = x_{t|t} + A_t (x_{t+1|T} - x_{t|t})   (eqn12, RTS reading)
+    HIPCK(gemv_smooth(p->Ab, ld, xf + (int64_t)t * N, xs + (int64_t)(t + 1) * N, xs + (int64_t)t * N, N, s));
+    if (mixed(p)) {
+        // D = P_{t+1|T} - P_t - Q in float32; M = A D; P_{t|T} = P_t + M A^T   (eqn13)
+        HIPCK(axpby3(N, N, p->D32, true, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
+        GemmProblem g;
+        g.M = N; g.N = N; g.K = N;
+        g.A = p->A32; g.lda = ld; g.B = p->D32; g.ldb = ld;
+        g.C32 = p->M32; g.ldc32 = ld;
+        TRY(big_gemm(p, Dt::F32, g, 2.0 * N * N * N));
+        GemmProblem h;
+        h.M = N; h.N = N; h.K = N;
+        h.A = p->M32; h.lda = ld; h.B = p->A32; h.ldb = ld; h.flags = G_TB | G_LOWER | G_MIRROR;
+        h.Cin = Pt64; h.ldcin = ld; h.beta = 1.0;
+        h.C = Ps_out; h.ldc = ld; h.diag = Pdiag;
+        TRY(big_gemm(p, Dt::F32, h, (double)N * N * N));
+    } else {
+        GemmProblem g;
+        g.M = N; g.N = N; g.K = N;
+        g.A = p->Ab; g.lda = ld;
+        g.B = Ps_next; g.ldb = ld;
+        g.B2 = Pt64; g.ldb2 = ld; g.b2coef = -1.0;
+        g.B3 = p->Q; g.ldb3 = ld; g.b3coef = -1.0;
+        g.C = p->W; g.ldc = ld;
+        TRY(big_gemm(p, Dt::F64, g, 2.0 * N * N * N));
+        GemmProblem h;
+        h.M = N; h.N = N; h.K = N;
+        h.A = p->W; h.lda = ld; h.B = p->Ab; h.ldb = ld; h.flags = G_TB | G_LOWER | G_MIRROR;
+        h.Cin = Pt64; h.ldcin = ld; h.beta = 1.0;
+        h.C = Ps_out; h.ldc = ld; h.diag = Pdiag;
+        TRY(big_gemm(p, Dt::F64, h, (double)N * N * N));
+    }
+    return KF_OK;
+}
+
+kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
+    hipStream_t s = p->stream;
+    const int64_t T = p->T_done, N = p->N;
+    const int64_t ld = p->ldN;
+    const bool s32 = p->store32;
+    const size_t esz = s32 ? 4 : 8;
+    const double* xf = p->xf_last;
+    HIPCK(hipMemsetAsync(p->dstatus, 0, 4 * sizeof(int), s));
+    // t = T-1: smoother = filter
+    const void* PT = slot_ptr(p, slot_of(p, T - 1, T));
+    HIPCK(copy2d((int)N, (int)N, p->Ps[(T - 1) & 1], false, ld, PT, s32, ld, s));
+    HIPCK(hipMemcpyAsync(xs + (T - 1) * N, xf + (T - 1) * N, N * 8, hipMemcpyDeviceToDevice, s));
+    if (Pdiag) HIPCK(diag_copy(p->Ps[(T - 1) & 1], ld, (int)N, Pdiag + (T - 1) * N, s));
+    if (Pfull)
+        HIPCK(hipMemcpy2DAsync(Pfull + (T - 1) * N * N, N * 8, p->Ps[(T - 1) & 1], ld * 8, N * 8, N,
+                               hipMemcpyDeviceToDevice, s));
+    int64_t seg_lo = -1, seg_hi = -2;
+    for (int64_t t = T - 2; t >= 0; --t) {
+        const void* Pt;
+        if (kept(p, t, T)) {
+            Pt = slot_ptr(p, slot_of(p, t, T));
+        } else {
+            if (t < seg_lo || t > seg_hi) {
+                // segment of non-kept steps containing t: (previous checkpoint, t]
+                const int64_t lo = (t + 1) / p->stride * p->stride;   // first step after the checkpoint
+                seg_lo = lo;
+                seg_hi = t;
+                TRY(recompute_segment(p, seg_lo, seg_hi, T));
+            }
+            Pt = static_cast<char*>(p->seg) + (size_t)(t - seg_lo) * slot_elems(p) * esz;
+        }
+        double* Ps_out = p->Ps[t & 1];
+        TRY(smooth_step(p, t, Pt, p->Ps[(t + 1) & 1], Ps_out, xf, xs, Pdiag ? Pdiag + t * N : nullptr));
+        if (Pfull)
+            HIPCK(hipMemcpy2DAsync(Pfull + t * N * N, N * 8, Ps_out, ld * 8, N * 8, N, hipMemcpyDeviceToDevice, s));
+    }
+    kf_status st = sync_and_check(p, "kf_smooth");
+    if (st == KF_OK && p->prof) TRY(collect_profile(p));
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+kf_status kf_smooth(kf_plan* p, double* x_smooth, double* Pdiag_smooth, double* P_smooth) {
+    if (!p) return KF_EINVAL;
+    p->err.clear();
+    if (p->T_done <= 0 || !p->xf_last) {
+        p->err = "kf_smooth: no completed kf_filter on this plan";
+        return KF_ESTATE;
+    }
+    if (!x_smooth) {
+        p->err = "kf_smooth: x_smooth is null";
+        return KF_EINVAL;
+    }
+    return smooth_impl(p, x_smooth, Pdiag_smooth, P_smooth);
+}
+
+kf_status kf_get_filtered_cov(kf_plan* p, int64_t t, double* P_out) {
+    if (!p) return KF_EINVAL;
+    p->err.clear();
+    if (p->T_done <= 0) {
+        p->err = "kf_get_filtered_cov: no completed kf_filter";
+        return KF_ESTATE;
+    }
+    if (t < 1 || t > p->T_done || !P_out) {
+        p->err = "kf_get_filtered_cov: need 1 <= t <= T and non-null P_out";
+        return KF_EINVAL;
+    }
+    const int64_t T = p->T_done, i = t - 1;
+    if (!kept(p, i, T)) {
+        const int64_t lo = (i + 1) / p->stride * p->stride;
+        TRY(recompute_segment(p, lo, i, T));
+        const size_t esz = p->store32 ? 4 : 8;
+        const void* src = static_cast<char*>(p->seg) + (size_t)(i - lo) * slot_elems(p) * esz;
+        HIPCK(copy2d((int)p->N, (int)p->N, P_out, false, p->N, src, p->store32, p->ldN, p->stream));
+    } else {
+        HIPCK(copy2d((int)p->N, (int)p->N, P_out, false, p->N, slot_ptr(p, slot_of(p, i, T)), p->store32, p->ldN,
+                     p->stream));
+    }
+    HIPCK(hipStreamSynchronize(p->stream));
+    return KF_OK;
+}
+
+kf_status kf_set_profiling(kf_plan* p, int on) {
+    if (!p) return KF_EINVAL;
+    p->prof = on != 0;
+    p->prof_ms = 0.0;
+    p->prof_flops = 0.0;
+    p->prof_launches = 0;
+    p->ev_used = 0;
+    p->ev_flops.clear();
+    return KF_OK;
+}
+
+kf_status kf_get_profile(const kf_plan* p, double* kernel_ms, double* kernel_flops, int64_t* launches) {
+    if (!p) return KF_EINVAL;
+    if (kernel_ms) *kernel_ms = p->prof_ms;
+    if (kernel_flops) *kernel_flops = p->prof_flops;
+    if (launches) *launches = p->prof_launches;
+    return KF_OK;
+}
+
+void kf_destroy(kf_plan* p) {
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    else (void)hipDeviceSynchronize();
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    for (void* a : p->allocs) (void)hipFree(a);
+    if (p->hstatus) (void)hipHostFree(p->hstatus);
+    delete p;
+}
+
+const char* kf_last_error(const kf_plan* p) { return p ? p->err.c_str() : g_err.c_str(); }
+
+kf_status mne_solve(int64_t N, int64_t m, int64_t T, const double* X, const double* C, const double* R,
+                    const double* Y, double* J, void* stream) {
+    g_err.clear();
+    if (N <= 0 || m <= 0 || T <= 0 || !X || !C || !R || !Y || !J) {
+        g_err = "mne_solve: sizes must be positive and pointers non-null";
+        return KF_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    kf_plan tmp;   // only for the error string and allocation bookkeeping
+    kf_plan* p = &tmp;
+    const int64_t ldm = round_up(m, 16), ldT = round_up(T, 16);
+    double *G, *S, *Lis, *U, *V, *part;
+    int* status;
+    int hstat[4] = {0, 0, 0, 0};
+    kf_status st = KF_OK;
+    auto cleanup = [&](kf_status r) {
+        for (void* a : tmp.allocs) (void)hipFree(a);
+        tmp.allocs.clear();
+        if (r != KF_OK && g_err.empty()) g_err = tmp.err;
+        return r;
+    };
+#define MALLOC(ptr, n)                                       \
+    if ((st = alloc(p, &(ptr), (n))) != KF_OK) return cleanup(st);
+    MALLOC(G, (size_t)N * ldm);
+    MALLOC(S, (size_t)m * ldm);
+    MALLOC(Lis, (size_t)m * ldm);
+    MALLOC(U, (size_t)m * ldT);
+    MALLOC(V, (size_t)m * ldT);
+    MALLOC(part, (size_t)32 * m * m);
+    MALLOC(status, 4);
+#undef MALLOC
+    auto run = [&]() -> kf_status {
+        HIPCK(hipMemsetAsync(status, 0, 4 * sizeof(int), s));
+        GemmProblem g;                       // G = C X^T   (N x m)
+        g.M = (int)N; g.N = (int)m; g.K = (int)N;
+        g.A = C; g.lda = N; g.B = X; g.ldb = N; g.flags = G_TB;
+        g.C = G; g.ldc = ldm;
+        HIPCK(gemm1(Dt::F64, g, s));
+        GemmProblem h;                       // S = X G + R
+        h.M = (int)m; h.N = (int)m; h.K = (int)N;
+        h.A = X; h.lda = N; h.B = G; h.ldb = ldm;
+        h.Cin = R; h.ldcin = m; h.beta = 1.0;
+        h.C = S; h.ldc = ldm;
+        h.ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(32, N / 128));
+        h.partial = part;
+        HIPCK(gemm1(Dt::F64, h, s));
+        HIPCK(chol_inv(S, ldm, Lis, ldm, (int)m, status, W_MNE, 0, s));
+        GemmProblem u;                       // U = Li Y^T   (m x T)
+        u.M = (int)m; u.N = (int)T; u.K = (int)m;
+        u.A = Lis; u.lda = ldm; u.flags = G_ALOWER | G_TB;
+        u.B = Y; u.ldb = m;
+        u.C = U; u.ldc = ldT;
+        HIPCK(gemm1(Dt::F64, u, s));
+        GemmProblem v;                       // V = Li^T U = S^{-1} Y^T
+        v.M = (int)m; v.N = (int)T; v.K = (int)m;
+        v.A = Lis; v.lda = ldm; v.flags = G_TA;
+        v.B = U; v.ldb = ldT;
+        v.C = V; v.ldc = ldT;
+        HIPCK(gemm1(Dt::F64, v, s));
+        GemmProblem j;                       // J = V^T G^T   (T x N)
+        j.M = (int)T; j.N = (int)N; j.K = (int)m;
+        j.A = V; j.lda = ldT; j.flags = G_TA | G_TB;
+        j.B = G; j.ldb = ldm;
+        j.C = J; j.ldc = N;
+        HIPCK(gemm1(Dt::F64, j, s));
+        HIPCK(hipMemcpyAsync(hstat, status, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        if (hstat[0]) {
+            p->err = "mne_solve: X C X^T + R is not positive definite (pivot row " + std::to_string(hstat[3]) + ")";
+            return KF_ENOTPD;
+        }
+        return KF_OK;
+    };
+    st = run();
+    if (st != KF_OK) g_err = tmp.err;
+    return cleanup(st);
+}
+
+}  // extern "C"

@@ -1,0 +1,370 @@
+// Grouped MFMA GEMM for gfx950 (CDNA4), float64 or float32 operands.
+//
+// One launch runs up to kMaxGroup independent problems; each workgroup owns a
+// 128 x 128 output tile of one problem. Four 64-wide waves each hold a 64 x 64
+// sub-tile as 4 x 4 blocks of the 16x16x4 MFMA (f64 or f32), so every operand
+// fragment read from LDS feeds four MFMAs. Operand tiles of 16 k-steps are
+// staged through double-buffered LDS in a fixed [k][row] layout whatever the
+// global layout (transposing loads are done on the way in), with one barrier
+// per k-tile; the next tile's global loads are in flight while the current
+// one is multiplied.
+//
+// Used for every dense product of the filter and smoother: X P_{t|t-1} and
+// X P X^T (eqn8), the rank-m downdate of the covariance update after eqn10,
+// the trailing updates of the blocked Cholesky, the triangular products that
+// form the smoother gain A_t (eqn11), A_t (P_{t+1|T} - P_{t+1|t}) and its
+// product with A_t^T (eqn13).
+#include "kf_internal.h"
+
+#include <algorithm>
+
+namespace kfmeg {
+
+namespace {
+
+constexpr int BM = 128, BN = 128, BK = 16, NT = 256;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> {
+    using V = d4;
+    static __device__ __forceinline__ V mfma(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Acc<float> {
+    using V = f4;
+    static __device__ __forceinline__ V mfma(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+enum : int { G_SCALAR = 1 << 20 };   // internal: operands not 16-byte aligned -> scalar loads
+
+// Load 8 consecutive elements p[0..7]; element q is valid iff q < nvalid.
+template <typename T>
+__device__ __forceinline__ void load8(T (&r)[8], const T* p, int nvalid, bool vec_ok) {
+    if (nvalid >= 8 && vec_ok) {
+        if constexpr (sizeof(T) == 8) {
+            const d2* v = reinterpret_cast<const d2*>(p);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { d2 t = v[q]; r[2 * q] = t.x; r[2 * q + 1] = t.y; }
+        } else {
+            const f4* v = reinterpret_cast<const f4*>(p);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                f4 t = v[q];
+                r[4 * q] = t.x; r[4 * q + 1] = t.y; r[4 * q + 2] = t.z; r[4 * q + 3] = t.w;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[q] = (q < nvalid) ? p[q] : T(0);
+    }
+}
+
+// Operand A tile: rows i0..i0+BM, k in [k0, k0+BK) clipped to [.., khi); into regs.
+template <typename T>
+__device__ __forceinline__ void fetch_a(T (&r)[8], const GemmProblem& P, int i0, int k0, int khi, int tid) {
+    const T* A = static_cast<const T*>(P.A);
+    const bool vec = !(P.flags & G_SCALAR);
+    if (!(P.flags & G_TA)) {            // A[i*lda + k]: row r, 8 consecutive k
+        const int rr = tid & (BM - 1), ks = (tid >> 7) * 8;
+        const int gi = i0 + rr, gk = k0 + ks;
+        const int nv = (gi < P.M) ? min(8, khi - gk) : 0;
+        if (nv > 0) load8<T>(r, A + (int64_t)gi * P.lda + gk, nv, vec);
+        else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = T(0);
+        }
+    } else {                            // A[k*lda + i]: k row, 8 consecutive i
+        const int kr = tid >> 4, is = (tid & 15) * 8;
+        const int gk = k0 + kr, gi = i0 + is;
+        const int nv = (gk < khi) ? min(8, P.M - gi) : 0;
+        if (nv > 0) load8<T>(r, A + (int64_t)gk * P.lda + gi, nv, vec);
+        else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = T(0);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void fetch_b_one(T (&r)[8], const T* B, int64_t ldb, bool tb, const GemmProblem& P,
+                                            int j0, int k0, int khi, int tid, bool vec) {
+    if (!tb) {                          // B[k*ldb + j]: k row, 8 consecutive j
+        const int kr = tid >> 4, js = (tid & 15) * 8;
+        const int gk = k0 + kr, gj = j0 + js;
+        const int nv = (gk < khi) ? min(8, P.N - gj) : 0;
+        if (nv > 0) load8<T>(r, B + (int64_t)gk * ldb + gj, nv, vec);
+        else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = T(0);
+        }
+    } else {                            // B[j*ldb + k]: row j, 8 consecutive k
+        const int rr = tid & (BN - 1), ks = (tid >> 7) * 8;
+        const int gj = j0 + rr, gk = k0 + ks;
+        const int nv = (gj < P.N) ? min(8, khi - gk) : 0;
+        if (nv > 0) load8<T>(r, B + (int64_t)gj * ldb + gk, nv, vec);
+        else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = T(0);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void fetch_b(T (&r)[8], const GemmProblem& P, int j0, int k0, int khi, int tid) {
+    const bool tb = P.flags & G_TB;
+    const bool vec = !(P.flags & G_SCALAR);
+    fetch_b_one<T>(r, static_cast<const T*>(P.B), P.ldb, tb, P, j0, k0, khi, tid, vec);
+    if (P.B2) {
+        T r2[8];
+        fetch_b_one<T>(r2, static_cast<const T*>(P.B2), P.ldb2, tb, P, j0, k0, khi, tid, vec);
+        const T c = (T)P.b2coef;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[q] += c * r2[q];
+    }
+    if (P.B3) {
+        T r3[8];
+        fetch_b_one<T>(r3, static_cast<const T*>(P.B3), P.ldb3, tb, P, j0, k0, khi, tid, vec);
+        const T c = (T)P.b3coef;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[q] += c * r3[q];
+    }
+}
+
+// Write the staged registers into the [k][row] LDS tile.
+template <typename T>
+__device__ __forceinline__ void stash(T* S, const T (&r)[8], bool transposing, int tid) {
+    if (transposing) {                  // regs hold 8 consecutive k of one row
+        const int rr = tid & 127, ks = (tid >> 7) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) S[(ks + q) * BM + rr] = r[q];
+    } else {                            // regs hold 8 consecutive rows of one k
+        const int kr = tid >> 4, is = (tid & 15) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) S[kr * BM + is + q] = r[q];
+    }
+}
+
+__device__ __forceinline__ double load_any(const void* p, bool f32, int64_t idx) {
+    return f32 ? (double)static_cast<const float*>(p)[idx] : static_cast<const double*>(p)[idx];
+}
+
+// Map a linear tile index onto (bm, bn) of the lower triangle bm >= bn.
+__device__ __forceinline__ void tri_decode(int t, int& bm, int& bn) {
+    int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    while (r * (r + 1) / 2 > t) --r;
+    bm = r;
+    bn = t - r * (r + 1) / 2;
+}
+
+// V selects a separately named instantiation: 0 for general products, 1 for the
+// smoother's N x N x N products (so profilers report them on their own).
+template <typename T, int V>
+__global__ __launch_bounds__(NT) void gemm_kernel(GemmGroup G) {
+    __shared__ T As[2][BK * BM];
+    __shared__ T Bs[2][BK * BN];
+    using AV = typename Acc<T>::V;
+
+    const int tid = threadIdx.x;
+    const int bid = blockIdx.x;
+    int q = 0;
+#pragma unroll
+    for (int u = 1; u < kMaxGroup; ++u)
+        if (u < G.count && bid >= G.p[u].tile_begin) q = u;
+    const GemmProblem& P = G.p[q];
+
+    int local = bid - P.tile_begin;
+    const int split = local % P.ksplit;
+    local /= P.ksplit;
+    int bm, bn;
+    if (P.flags & G_LOWER) tri_decode(local, bm, bn);
+    else { bm = local / P.tiles_n; bn = local - bm * P.tiles_n; }
+    const int i0 = bm * BM, j0 = bn * BN;
+
+    // K range of this tile (triangular operands hold explicit zeros, so trimming is exact).
+    int klo = 0, khi = P.K;
+    if (P.flags & G_ALOWER) khi = min(khi, i0 + BM);
+    if (P.flags & G_BUPPER) khi = min(khi, j0 + BN);
+    if (P.flags & G_BLOWER) klo = max(klo, j0);
+    if (P.ksplit > 1) {
+        const int span = max(khi - klo, 0);
+        const int chunk = ((span + P.ksplit - 1) / P.ksplit + BK - 1) / BK * BK;
+        const int a = klo + split * chunk;
+        klo = a;
+        khi = min(khi, a + chunk);
+    }
+    const int nk = khi > klo ? (khi - klo + BK - 1) / BK : 0;
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    AV acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = AV{0, 0, 0, 0};
+
+    const bool ta_transposing = !(P.flags & G_TA);
+    const bool tb_transposing = (P.flags & G_TB);
+
+    if (nk > 0) {
+        T ra[8], rb[8];
+        fetch_a<T>(ra, P, i0, klo, khi, tid);
+        fetch_b<T>(rb, P, j0, klo, khi, tid);
+        stash<T>(As[0], ra, ta_transposing, tid);
+        stash<T>(Bs[0], rb, tb_transposing, tid);
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            const bool more = kt + 1 < nk;
+            if (more) {
+                const int k0 = klo + (kt + 1) * BK;
+                fetch_a<T>(ra, P, i0, k0, khi, tid);
+                fetch_b<T>(rb, P, j0, k0, khi, tid);
+            }
+            const T* as = As[cur];
+            const T* bs = Bs[cur];
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                T fa[4], fb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) fa[a] = as[(kk + lk) * BM + wm + a * 16 + lr];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) fb[b] = bs[(kk + lk) * BN + wn + b * 16 + lr];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = Acc<T>::mfma(fa[a], fb[b], acc[a][b]);
+            }
+            if (more) {
+                stash<T>(As[cur ^ 1], ra, ta_transposing, tid);
+                stash<T>(Bs[cur ^ 1], rb, tb_transposing, tid);
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- epilogue. Lane holds acc[a][b][r] = C(i0+wm+16a+4*lk+r, j0+wn+16b+lr).
+    if (P.ksplit > 1) {
+        T* part = static_cast<T*>(P.partial) + (int64_t)split * P.M * P.N;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + wm + 16 * a + 4 * lk + r, j = j0 + wn + 16 * b + lr;
+                    if (i < P.M && j < P.N) part[(int64_t)i * P.N + j] = acc[a][b][r];
+                }
+        return;
+    }
+    const bool lower = P.flags & G_LOWER, mirror = P.flags & G_MIRROR;
+    const bool cin32 = P.flags & G_CIN32, cin2_32 = P.flags & G_CIN2_32;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wm + 16 * a + 4 * lk + r, j = j0 + wn + 16 * b + lr;
+                if (i >= P.M || j >= P.N) continue;
+                if (lower && j > i) continue;
+                double v = P.alpha * (double)acc[a][b][r];
+                if (P.Cin) v += P.beta * load_any(P.Cin, cin32, (int64_t)i * P.ldcin + j);
+                if (P.Cin2) v += P.gamma * load_any(P.Cin2, cin2_32, (int64_t)i * P.ldcin2 + j);
+                if (P.C) P.C[(int64_t)i * P.ldc + j] = v;
+                if (P.C32) P.C32[(int64_t)i * P.ldc32 + j] = (float)v;
+                if (P.diag && i == j) P.diag[i] = v;
+                if (mirror && i > j) {
+                    if (P.C) P.C[(int64_t)j * P.ldc + i] = v;
+                    if (P.C32) P.C32[(int64_t)j * P.ldc32 + i] = (float)v;
+                }
+            }
+}
+
+// Split-K reduction in fixed split order (deterministic), then the epilogue.
+template <typename T>
+__global__ void gemm_reduce_kernel(GemmProblem P) {
+    const int64_t n = (int64_t)P.M * P.N;
+    const T* part = static_cast<const T*>(P.partial);
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / P.N), j = (int)(idx - (int64_t)i * P.N);
+        if ((P.flags & G_LOWER) && j > i) continue;
+        double s = 0.0;
+        for (int sp = 0; sp < P.ksplit; ++sp) s += (double)part[sp * n + idx];
+        double v = P.alpha * s;
+        if (P.Cin) v += P.beta * load_any(P.Cin, P.flags & G_CIN32, (int64_t)i * P.ldcin + j);
+        if (P.Cin2) v += P.gamma * load_any(P.Cin2, P.flags & G_CIN2_32, (int64_t)i * P.ldcin2 + j);
+        if (P.C) P.C[(int64_t)i * P.ldc + j] = v;
+        if (P.C32) P.C32[(int64_t)i * P.ldc32 + j] = (float)v;
+        if (P.diag && i == j) P.diag[i] = v;
+        if ((P.flags & G_MIRROR) && i > j) {
+            if (P.C) P.C[(int64_t)j * P.ldc + i] = v;
+            if (P.C32) P.C32[(int64_t)j * P.ldc32 + i] = (float)v;
+        }
+    }
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s) {
+    GemmGroup G;
+    int total = 0;
+    const int esz = dt == Dt::F64 ? 8 : 4;
+    const int vec_elems = 16 / esz;
+    for (int u = 0; u < count; ++u) {
+        GemmProblem p = probs[u];
+        if (p.M <= 0 || p.N <= 0) continue;
+        if (p.ksplit < 1) p.ksplit = 1;
+        p.tiles_m = (p.M + BM - 1) / BM;
+        p.tiles_n = (p.N + BN - 1) / BN;
+        if (p.flags & G_LOWER) {
+            if (p.M != p.N) return hipErrorInvalidValue;
+        }
+        bool vec = aligned16(p.A) && aligned16(p.B) && p.lda % vec_elems == 0 && p.ldb % vec_elems == 0;
+        if (p.B2) vec = vec && aligned16(p.B2) && p.ldb2 % vec_elems == 0;
+        if (p.B3) vec = vec && aligned16(p.B3) && p.ldb3 % vec_elems == 0;
+        if (!vec) p.flags |= G_SCALAR;
+        p.tile_begin = total;
+        const int tiles = (p.flags & G_LOWER) ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+        total += tiles * p.ksplit;
+        if (G.count >= kMaxGroup) return hipErrorInvalidValue;
+        G.p[G.count++] = p;
+    }
+    if (G.count == 0) return hipSuccess;
+    G.total_tiles = total;
+    const bool big = G.p[0].flags & G_NXN;
+    if (dt == Dt::F64) {
+        if (big) hipLaunchKernelGGL((gemm_kernel<double, 1>), dim3(total), dim3(NT), 0, s, G);
+        else hipLaunchKernelGGL((gemm_kernel<double, 0>), dim3(total), dim3(NT), 0, s, G);
+    } else {
+        if (big) hipLaunchKernelGGL((gemm_kernel<float, 1>), dim3(total), dim3(NT), 0, s, G);
+        else hipLaunchKernelGGL((gemm_kernel<float, 0>), dim3(total), dim3(NT), 0, s, G);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int u = 0; u < G.count; ++u) {
+        const GemmProblem& p = G.p[u];
+        if (p.ksplit <= 1) continue;
+        const int64_t n = (int64_t)p.M * p.N;
+        const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+        if (dt == Dt::F64) hipLaunchKernelGGL(gemm_reduce_kernel<double>, dim3(blocks), dim3(256), 0, s, p);
+        else hipLaunchKernelGGL(gemm_reduce_kernel<float>, dim3(blocks), dim3(256), 0, s, p);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace kfmeg

@@ -1,0 +1,97 @@
+// Internal interfaces of the kfmeg library: GEMM problem descriptors, the
+// blocked Cholesky-with-inverse driver and the small vector kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+
+namespace kfmeg {
+
+// ---------------------------------------------------------------- GEMM
+// C = alpha * op(A) op(B) + beta * Cin + gamma * Cin2, with op(B) = B + b2coef B2 + b3coef B3.
+// Operands are of the kernel's compute type (double or float); the epilogue is float64.
+enum GemmFlags : int {
+    G_TA = 1,          // A(i,k) = A[k*lda + i]   (else A[i*lda + k])
+    G_TB = 2,          // B(k,j) = B[j*ldb + k]   (else B[k*ldb + j])
+    G_LOWER = 4,       // square C: compute tiles on/below the diagonal, store i >= j only
+    G_MIRROR = 8,      // with G_LOWER: also store C(j,i) = C(i,j) (exactly symmetric result)
+    G_ALOWER = 16,     // A(i,k) = 0 for k > i (stored zeros): K range trimmed per tile
+    G_BLOWER = 32,     // B(k,j) = 0 for k < j
+    G_BUPPER = 64,     // B(k,j) = 0 for k > j
+    G_CIN32 = 128,     // Cin is float (else double)
+    G_CIN2_32 = 256,   // Cin2 is float (else double)
+    G_NXN = 512,       // launch the separately named instantiation for the smoother's N x N x N products
+};
+
+struct GemmProblem {
+    int M = 0, N = 0, K = 0, flags = 0;
+    const void* A = nullptr; int64_t lda = 0;
+    const void* B = nullptr; int64_t ldb = 0;
+    const void* B2 = nullptr; int64_t ldb2 = 0; double b2coef = 0.0;
+    const void* B3 = nullptr; int64_t ldb3 = 0; double b3coef = 0.0;
+    double alpha = 1.0, beta = 0.0, gamma = 0.0;
+    const void* Cin = nullptr; int64_t ldcin = 0;
+    const void* Cin2 = nullptr; int64_t ldcin2 = 0;
+    double* C = nullptr; int64_t ldc = 0;       // float64 output (may be null)
+    float* C32 = nullptr; int64_t ldc32 = 0;    // float32 output (may be null)
+    double* diag = nullptr;                     // C(i,i) for i < min(M,N) (may be null)
+    int ksplit = 1;                             // >1: raw partial sums to `partial`, epilogue by gemm_reduce
+    void* partial = nullptr;                    // [ksplit][M][N], compute type
+    // filled by the launcher
+    int tiles_m = 0, tiles_n = 0, tile_begin = 0;
+};
+
+constexpr int kMaxGroup = 4;
+struct GemmGroup {
+    GemmProblem p[kMaxGroup];
+    int count = 0;
+    int total_tiles = 0;
+};
+
+enum class Dt { F64, F32 };
+
+// Enqueue a group of up to kMaxGroup problems sharing one launch (compute type `dt`).
+// Problems with ksplit > 1 are followed by their reduction launch.
+hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s);
+inline hipError_t gemm1(Dt dt, GemmProblem p, hipStream_t s) { return gemm_launch(dt, &p, 1, s); }
+
+// ---------------------------------------------------------------- Cholesky + inverse
+// Device status word: first failure wins. [0] = failed (1), [1] = which matrix, [2] = step t,
+// [3] = row of the failing pivot.
+enum Which : int { W_S = 1, W_PPRED = 2, W_MNE = 3 };
+
+// Blocked right-looking Cholesky of the SPD matrix held in the lower triangle of W (n x n, ld ldw),
+// fused with the inverse of the factor: on return W's lower triangle holds L (strict upper zeroed)
+// and Z holds L^{-1} (lower; strict upper zeroed). Z must not alias W.
+hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, int* status,
+                    int which, int step, hipStream_t s);
+
+// ---------------------------------------------------------------- vector / elementwise kernels
+// e = y - X x  (X: m x N, ld ldx)
+hipError_t resid(const double* X, int64_t ldx, const double* x, const double* y, double* e,
+                 int m, int N, hipStream_t s);
+// w = Lower(L) e  (L: m x m, ld ldl; only the lower triangle is read)
+hipError_t trmv_lower(const double* L, int64_t ldl, const double* e, double* w, int m, hipStream_t s);
+// x_out = x_in + C^T w  (C: m x N, ld ldc); optional copy to x_copy
+hipError_t gemv_t_add(const double* C, int64_t ldc, const double* w, const double* x_in,
+                      double* x_out, double* x_copy, int m, int N, hipStream_t s);
+// out = x + A (v - x)   (A: N x N, ld lda)   -- smoothed mean (eqn12)
+hipError_t gemv_smooth(const double* A, int64_t lda, const double* x, const double* v,
+                       double* out, int N, hipStream_t s);
+// D = a + ca*b + cb*c for matrices (rows x cols); each source may be float or double
+hipError_t axpby3(int rows, int cols, void* D, bool d32, int64_t ldd,
+                  const void* a, bool a32, int64_t lda,
+                  const void* b, bool b32, int64_t ldb, double cb,
+                  const void* c, bool c32, int64_t ldc, double cc, hipStream_t s);
+// copy rows x cols between (possibly) different precisions and leading dimensions
+hipError_t copy2d(int rows, int cols, void* dst, bool d32, int64_t ldd,
+                  const void* src, bool s32, int64_t lds, hipStream_t s);
+// set a rows x cols block to zero
+hipError_t zero2d(int rows, int cols, double* dst, int64_t ldd, hipStream_t s);
+// scan n values for NaN / Inf; sets *flag = 1 if any
+hipError_t nonfinite_scan(const double* v, int64_t n, int* flag, hipStream_t s);
+// store diag of a square double matrix to out
+hipError_t diag_copy(const double* A, int64_t lda, int n, double* out, hipStream_t s);
+
+}  // namespace kfmeg

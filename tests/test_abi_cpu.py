@@ -1,0 +1,57 @@
+"""CPU checks of the boundary: the library loads and exports every function the header declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
+LIB = os.path.join(ROOT, "paper_1107_4192_amd", "libkfmeg.so")
+
+
+def declared_functions():
+    text = "\n".join(open(h).read() for h in HEADERS)
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_][a-z_0-9]*\s*\*?\s+\*?([a-z_][a-z_0-9]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("kf_create", "kf_filter", "kf_smooth", "mne_solve", "kf_destroy"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libkfmeg.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libkfmeg.so not built")
+def test_binding_lists_the_same_symbols():
+    from paper_1107_4192_amd import kfmeg
+    assert sorted(kfmeg.EXPORTS) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libkfmeg.so not built")
+def test_plan_bytes_host_logic():
+    from paper_1107_4192_amd import kfmeg
+    b64 = kfmeg.kf_plan_bytes(5124, 306, 200, kfmeg.options())
+    b32 = kfmeg.kf_plan_bytes(5124, 306, 200, kfmeg.options(store_fp32=True))
+    ck = kfmeg.kf_plan_bytes(5124, 306, 200, kfmeg.options(checkpoint_stride=14))
+    store64 = 200 * 5124 * 5136 * 8
+    assert b64 > store64 and b32 < b64 and ck < b64
+    assert kfmeg.kf_plan_bytes(0, 306, 200, None) == 0
+
+
+def test_product_path_has_no_oracle_import():
+    pkg = os.path.join(ROOT, "paper_1107_4192_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f

@@ -1,0 +1,128 @@
+"""GPU unit tests of the two building blocks, through the kernel-level C entry points.
+
+Each is compared with a plain float64 CPU computation of the same operation:
+the MFMA GEMM (every layout, triangular and split-K mode, float64 and float32
+operands, ragged sizes spanning several 128-tiles) and the blocked Cholesky
+fused with the inverse of its factor.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1107_4192_amd import kfmeg
+
+pytestmark = pytest.mark.gpu
+
+F = kfmeg
+
+
+def _op(X, trans):
+    return X.T if trans else X
+
+
+CASES = [
+    (1, 1, 1, 0), (15, 17, 3, 0), (64, 64, 64, 0), (128, 128, 16, 0), (130, 257, 33, 0),
+    (306, 500, 500, 0), (129, 129, 200, F.G_TA), (200, 77, 129, F.G_TB), (257, 140, 65, F.G_TA | F.G_TB),
+    (300, 300, 70, F.G_LOWER), (300, 300, 70, F.G_LOWER | F.G_MIRROR), (300, 300, 70, F.G_LOWER | F.G_MIRROR | F.G_TA),
+    (306, 306, 5124, F.G_TB),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("M,N,K,flags", CASES)
+@pytest.mark.parametrize("ksplit", [1, 3])
+def test_gemm_layouts(dtype, M, N, K, flags, ksplit):
+    g = torch.Generator().manual_seed(M * 7919 + N * 31 + K + flags * 101 + ksplit)
+    ta, tb = bool(flags & F.G_TA), bool(flags & F.G_TB)
+    A = torch.randn((K, M) if ta else (M, K), generator=g, dtype=torch.float64)
+    B = torch.randn((N, K) if tb else (K, N), generator=g, dtype=torch.float64)
+    Cin = torch.randn((M, N), generator=g, dtype=torch.float64)
+    alpha, beta = -0.75, 1.25
+    Ad, Bd = A.to(dtype), B.to(dtype)
+    ref = alpha * (_op(Ad.double(), ta) @ _op(Bd.double(), tb)) + beta * Cin
+    C = F.kfd_gemm(Ad.cuda(), Bd.cuda(), M, N, K, flags, alpha, beta, Cin.cuda(), ksplit=ksplit).cpu()
+    tol = (1e-13 if dtype == torch.float64 else 2e-6) * K ** 0.5 * 4 + (1e-14 if dtype == torch.float64 else 1e-6)
+    if flags & F.G_LOWER:
+        low = torch.tril(torch.ones(M, N, dtype=torch.bool))
+        assert (C[low] - ref[low]).abs().max() <= tol * max(1.0, ref.abs().max())
+        if flags & F.G_MIRROR:
+            assert torch.equal(C, C.T)
+        else:
+            assert torch.equal(C[~low], torch.zeros_like(C[~low]))
+    else:
+        assert (C - ref).abs().max() <= tol * max(1.0, ref.abs().max())
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n,k", [(200, 200), (300, 130), (129, 257)])
+def test_gemm_triangular_operands(dtype, n, k):
+    g = torch.Generator().manual_seed(n + k)
+    # A lower triangular (n x n) times B (n x k)
+    A = torch.tril(torch.randn(n, n, generator=g, dtype=torch.float64)).to(dtype)
+    B = torch.randn(n, k, generator=g, dtype=torch.float64).to(dtype)
+    C = F.kfd_gemm(A.cuda(), B.cuda(), n, k, n, F.G_ALOWER).cpu()
+    ref = A.double() @ B.double()
+    tol = 1e-12 if dtype == torch.float64 else 2e-5
+    assert (C - ref).abs().max() <= tol * ref.abs().max()
+    # G^T L with L lower (B lower: B(k,j) = 0 for k < j)
+    G = torch.randn(n, k, generator=g, dtype=torch.float64).to(dtype)
+    L = torch.tril(torch.randn(n, n, generator=g, dtype=torch.float64)).to(dtype)
+    C = F.kfd_gemm(G.cuda(), L.cuda(), k, n, n, F.G_TA | F.G_BLOWER).cpu()
+    ref = G.double().T @ L.double()
+    assert (C - ref).abs().max() <= tol * ref.abs().max()
+    # X L^T with L lower: B(k,j) = L[j][k], upper in (k,j)
+    X = torch.randn(k, n, generator=g, dtype=torch.float64).to(dtype)
+    C = F.kfd_gemm(X.cuda(), L.cuda(), k, n, n, F.G_TB | F.G_BUPPER).cpu()
+    ref = X.double() @ L.double().T
+    assert (C - ref).abs().max() <= tol * ref.abs().max()
+
+
+def test_gemm_padded_leading_dimension():
+    g = torch.Generator().manual_seed(5)
+    big = torch.randn(300, 400, generator=g, dtype=torch.float64)
+    A = big[:, :150]            # lda = 400
+    B = torch.randn(150, 260, generator=g, dtype=torch.float64)
+    C = F.kfd_gemm(big.cuda()[:, :150], B.cuda(), 300, 260, 150).cpu()
+    assert (C - A @ B).abs().max() <= 1e-12 * (A @ B).abs().max()
+
+
+def test_gemm_mfma_fragment_layout_single_tile():
+    # One 16 x 16 x 4 product with distinct entries pins the lane layout of the MFMA operands and result.
+    A = torch.arange(16 * 4, dtype=torch.float64).reshape(16, 4) / 7.0
+    B = (torch.arange(4 * 16, dtype=torch.float64).reshape(4, 16) - 30.0) / 3.0
+    C = F.kfd_gemm(A.cuda(), B.cuda(), 16, 16, 4).cpu()
+    assert torch.allclose(C, A @ B, rtol=1e-15, atol=1e-13)
+
+
+def _spd(n, seed, cond=1e3):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    ev = np.logspace(-np.log10(cond), 0, n)
+    A = (U * ev) @ U.T
+    return (A + A.T) / 2
+
+
+@pytest.mark.parametrize("n", [1, 2, 17, 63, 64, 65, 127, 128, 129, 200, 306, 500])
+def test_chol_inv(n):
+    A = _spd(n, n)
+    # the strict upper triangle is never read: fill it with garbage
+    W = torch.tril(torch.tensor(A, device="cuda")) + torch.triu(torch.full((n, n), 7.0, device="cuda", dtype=torch.float64), 1)
+    Z = F.kfd_chol_inv(W)
+    L = W.cpu().numpy()
+    Li = Z.cpu().numpy()
+    Lref = np.linalg.cholesky(A)
+    assert np.abs(L - Lref).max() <= 1e-12 * np.abs(Lref).max() * max(1, n) ** 0.5
+    assert np.array_equal(np.triu(L, 1), np.zeros((n, n)))
+    assert np.array_equal(np.triu(Li, 1), np.zeros((n, n)))
+    assert np.abs(Li @ Lref - np.eye(n)).max() <= 1e-11 * max(1, n) ** 0.5 * 30
+
+
+def test_chol_inv_reports_first_bad_pivot():
+    n = 150
+    A = _spd(n, 3, cond=10)
+    A[100, 100] = -1.0
+    W = torch.tensor(A, device="cuda")
+    with pytest.raises(kfmeg.KFError) as ei:
+        F.kfd_chol_inv(W)
+    assert ei.value.status == kfmeg.KF_ENOTPD
+    assert "pivot row 100" in str(ei.value)

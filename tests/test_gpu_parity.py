@@ -1,0 +1,183 @@
+"""Parity of the HIP filter/smoother/MNE path with the FP64 oracle, through the C ABI.
+
+Tolerances (normwise per step, max over steps; see _helpers): 1e-10 for the
+float64 path, 1e-4 for mixed precision. Sizes span several 128-tiles with
+ragged tails, the degenerate one-dimensional case, and the paper-scale shape
+(N=5124, m=306) on a short horizon whose outputs the oracle computes in seconds.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1107_4192_amd import kfmeg, synth
+from _helpers import dev, eps_P, eps_d, eps_x, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOLMIX = 1e-4
+
+
+def gpu_run(p, T=None, full=False, **opt):
+    T = p.T if T is None else T
+    ks = kfmeg.KalmanSmoother(dev(p.X), dev(p.Q), dev(p.R), dev(p.x0), dev(p.P0), T_max=T, **opt)
+    try:
+        res = ks.run(dev(p.Y[:T]), want_full=full)
+        filt = [to_np(ks.filtered_cov(t + 1)) for t in range(T)] if full else None
+    finally:
+        ks.close()
+    return res, filt
+
+
+def oracle_run(p, T=None):
+    T = p.T if T is None else T
+    xf, Pf, dPf = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, p.Y[:T])
+    xs, Ps, dPs = oracle.rts_smooth(xf, Pf, p.Q)
+    return xf, Pf, dPf, xs, Ps, dPs
+
+
+def check_all(res, filt, ref, tol):
+    xf, Pf, dPf, xs, Ps, dPs = ref
+    errs = {
+        "x_filt": eps_x(res.x_filt, xf), "d_filt": eps_d(res.Pdiag_filt, dPf),
+        "x_smooth": eps_x(res.x_smooth, xs), "d_smooth": eps_d(res.Pdiag_smooth, dPs),
+    }
+    if filt is not None:
+        errs["P_filt"] = eps_P(np.stack(filt), Pf)
+    if res.P_smooth is not None:
+        errs["P_smooth"] = eps_P(res.P_smooth, Ps)
+    assert max(errs.values()) <= tol, errs
+    return errs
+
+
+@pytest.mark.parametrize("seed,N,m,T", [(1, 1, 1, 5), (2, 5, 3, 4), (3, 20, 6, 10), (4, 130, 7, 5),
+                                        (5, 257, 130, 4), (6, 64, 64, 3)])
+def test_small_random_vs_oracle_and_brute_force(seed, N, m, T):
+    p = synth.small_random(seed, N, m, T)
+    res, filt = gpu_run(p, full=True)
+    ref = oracle_run(p)
+    check_all(res, filt, ref, TOL64)
+    if N * T <= 200:
+        bf = oracle.joint_posterior(p.X, p.Q, p.R, p.x0, p.P0, p.Y)
+        assert eps_x(res.x_smooth, bf[2]) <= TOL64
+        assert eps_P(res.P_smooth, bf[3]) <= TOL64
+
+
+def test_tiny_workload_full_parity():
+    p = synth.tiny()
+    res, filt = gpu_run(p, full=True)
+    errs = check_all(res, filt, oracle_run(p), TOL64)
+    print("tiny fp64 errors", errs)
+    # exact symmetry of every stored and smoothed covariance
+    Ps = to_np(res.P_smooth)
+    assert np.array_equal(Ps, np.transpose(Ps, (0, 2, 1)))
+    assert all(np.array_equal(P, P.T) for P in filt)
+
+
+def test_tiny_workload_mixed_precision():
+    p = synth.tiny()
+    res, _ = gpu_run(p, precision=kfmeg.KF_MIXED, store_fp32=True)
+    errs = check_all(res, None, oracle_run(p), TOLMIX)
+    print("tiny mixed errors", errs)
+
+
+def test_store_fp32_with_fp64_arithmetic():
+    p = synth.tiny(T=20)
+    res, _ = gpu_run(p, store_fp32=True)
+    ref = oracle_run(p)
+    # the filter never reads the store: exact to the fp64 bar
+    assert eps_x(res.x_filt, ref[0]) <= TOL64 and eps_d(res.Pdiag_filt, ref[2]) <= TOL64
+    errs = check_all(res, None, ref, TOLMIX)
+    print("fp32 store errors", errs)
+
+
+def test_checkpoint_recompute_matches_store_all_bitwise():
+    p = synth.tiny(T=23)
+    a, fa = gpu_run(p, full=True)
+    b, fb = gpu_run(p, full=True, checkpoint_stride=5)
+    for u, v in ((a.x_smooth, b.x_smooth), (a.Pdiag_smooth, b.Pdiag_smooth), (a.P_smooth, b.P_smooth)):
+        assert torch.equal(u, v)
+    assert all(np.array_equal(u, v) for u, v in zip(fa, fb))
+
+
+def test_checkpoint_forced_by_budget():
+    p = synth.tiny(T=30)
+    need = kfmeg.kf_plan_bytes(500, 60, 30, kfmeg.options())
+    a, _ = gpu_run(p)
+    b, _ = gpu_run(p, hbm_budget_bytes=int(need * 0.6))
+    assert torch.equal(a.x_smooth, b.x_smooth) and torch.equal(a.Pdiag_smooth, b.Pdiag_smooth)
+
+
+def test_deterministic_and_data_independent_covariances():
+    p = synth.tiny(T=12)
+    a, fa = gpu_run(p, full=True)
+    b, fb = gpu_run(p, full=True)
+    assert torch.equal(a.x_smooth, b.x_smooth) and torch.equal(a.P_smooth, b.P_smooth)
+    p.Y = np.random.default_rng(9).normal(size=p.Y.shape)
+    c, fc = gpu_run(p, full=True)
+    assert torch.equal(a.P_smooth, c.P_smooth) and all(np.array_equal(u, v) for u, v in zip(fa, fc))
+
+
+def test_paper_scale_short_horizon():
+    """N=5124, m=306 (the paper's shape) on T=3: every output of the oracle, element by element."""
+    p = synth.paper(T=3)
+    res, _ = gpu_run(p, full=True)
+    ref = oracle_run(p)
+    errs = check_all(res, None, ref, TOL64)
+    print("paper-scale fp64 errors", errs)
+
+
+def test_mne_solve_vs_oracle():
+    p = synth.tiny(T=7)
+    rng = np.random.default_rng(3)
+    for C in (0.7 * np.eye(p.N), np.diag(rng.uniform(0.5, 2.0, p.N))):
+        J = kfmeg.mne_solve(dev(p.X), dev(C), dev(p.R), dev(p.Y))
+        ref = oracle.mne_solve(p.X, C, p.R, p.Y)
+        assert eps_x(J, ref) <= TOL64
+    # ragged, several tiles
+    q = synth.small_random(8, 300, 130, 9)
+    J = kfmeg.mne_solve(dev(q.X), dev(q.P0), dev(q.R), dev(q.Y))
+    assert eps_x(J, oracle.mne_solve(q.X, q.P0, q.R, q.Y)) <= TOL64
+
+
+def test_mne_equals_first_kalman_step_on_gpu():
+    p = synth.tiny(T=1)
+    res, _ = gpu_run(p)
+    J = kfmeg.mne_solve(dev(p.X), dev(p.P0 + p.Q), dev(p.R), dev(p.Y))
+    assert eps_x(res.x_filt, J) <= TOL64
+
+
+# ---------------------------------------------------------------- error paths
+def test_nan_data_rejected():
+    p = synth.tiny(T=5)
+    p.Y[3, 7] = np.nan
+    with pytest.raises(kfmeg.KFError) as ei:
+        gpu_run(p)
+    assert ei.value.status == kfmeg.KF_EINVAL
+
+
+def test_non_pd_innovation_reports_step():
+    p = synth.tiny(T=5)
+    p.R = -np.eye(p.m)
+    p.Q = np.zeros_like(p.Q)
+    p.P0 = np.zeros_like(p.P0)
+    with pytest.raises(kfmeg.KFError) as ei:
+        gpu_run(p)
+    assert ei.value.status == kfmeg.KF_ENOTPD
+    assert "t=1" in str(ei.value)
+
+
+def test_smooth_before_filter_is_state_error():
+    p = synth.tiny(T=4)
+    ks = kfmeg.KalmanSmoother(dev(p.X), dev(p.Q), dev(p.R), dev(p.x0), dev(p.P0), T_max=4)
+    try:
+        out = torch.empty((4, p.N), dtype=torch.float64, device="cuda")
+        with pytest.raises(kfmeg.KFError) as ei:
+            kfmeg.kf_smooth(ks.plan, out)
+        assert ei.value.status == kfmeg.KF_ESTATE
+        with pytest.raises(kfmeg.KFError) as ei:
+            ks.filter(dev(np.zeros((5, p.m))))        # T > T_max
+        assert ei.value.status == kfmeg.KF_EINVAL
+    finally:
+        ks.close()
