@@ -34,8 +34,9 @@ int kfd_gemm(int dtype, int M, int N, int K, int flags, const void* A, int64_t l
 
 /*
  * Cholesky factor and its inverse of the SPD matrix in the lower triangle of
- * W (n x n, ld ldw): on return W holds L (strict upper zeroed) and Z (n x n,
- * ld ldz) holds L^{-1}. Returns 0, or 2 with *pivot_row set if a pivot is not
+ * W (n x n, ld ldw): on return the lower triangle of W holds L (the strict
+ * upper triangle is not part of the result) and Z (n x n, ld ldz) holds
+ * L^{-1}, lower triangular with explicit zeros above the diagonal. Returns 0, or 2 with *pivot_row set if a pivot is not
  * positive (or not finite), 1 on bad arguments, 4 on a HIP error.
  */
 int kfd_chol_inv(int n, double* W, int64_t ldw, double* Z, int64_t ldz, int* pivot_row, void* stream);

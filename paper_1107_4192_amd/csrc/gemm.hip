@@ -28,15 +28,19 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
+// Result layout of the 16x16x4 MFMA: lane (lk = lane/16, lr = lane%16) holds C(row, lr) in
+// register r, with row = lk + 4 r for f64 and row = 4 lk + r for f32.
 template <typename T> struct Acc;
 template <> struct Acc<double> {
     using V = d4;
+    static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
     static __device__ __forceinline__ V mfma(double a, double b, V c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
 };
 template <> struct Acc<float> {
     using V = f4;
+    static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
     static __device__ __forceinline__ V mfma(float a, float b, V c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmGroup G) {
         }
     }
 
-    // ---- epilogue. Lane holds acc[a][b][r] = C(i0+wm+16a+4*lk+r, j0+wn+16b+lr).
+    // ---- epilogue. Lane holds acc[a][b][r] = C(i0+wm+16a+row(lk,r), j0+wn+16b+lr).
     if (P.ksplit > 1) {
         T* part = static_cast<T*>(P.partial) + (int64_t)split * P.M * P.N;
 #pragma unroll
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmGroup G) {
             for (int b = 0; b < 4; ++b)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int i = i0 + wm + 16 * a + 4 * lk + r, j = j0 + wn + 16 * b + lr;
+                    const int i = i0 + wm + 16 * a + Acc<T>::row(lk, r), j = j0 + wn + 16 * b + lr;
                     if (i < P.M && j < P.N) part[(int64_t)i * P.N + j] = acc[a][b][r];
                 }
         return;
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmGroup G) {
         for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wm + 16 * a + 4 * lk + r, j = j0 + wn + 16 * b + lr;
+                const int i = i0 + wm + 16 * a + Acc<T>::row(lk, r), j = j0 + wn + 16 * b + lr;
                 if (i >= P.M || j >= P.N) continue;
                 if (lower && j > i) continue;
                 double v = P.alpha * (double)acc[a][b][r];

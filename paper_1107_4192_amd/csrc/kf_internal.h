@@ -62,8 +62,9 @@ inline hipError_t gemm1(Dt dt, GemmProblem p, hipStream_t s) { return gemm_launc
 enum Which : int { W_S = 1, W_PPRED = 2, W_MNE = 3 };
 
 // Blocked right-looking Cholesky of the SPD matrix held in the lower triangle of W (n x n, ld ldw),
-// fused with the inverse of the factor: on return W's lower triangle holds L (strict upper zeroed)
-// and Z holds L^{-1} (lower; strict upper zeroed). Z must not alias W.
+// fused with the inverse of the factor: on return W's lower triangle holds L (its strict upper
+// triangle is scratch) and Z holds L^{-1} (lower, explicit zeros above the diagonal). Z must not
+// alias W.
 hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, int* status,
                     int which, int step, hipStream_t s);
 
