@@ -1,71 +1,116 @@
-// Blocked Cholesky factorisation fused with the inverse of the factor (float64).
+// Blocked Cholesky factorisation fused with the inverse of the factor (float64),
+// for a batch of independent matrices.
 //
 // The filter needs S^{-1} in eqn8/eqn9 and the smoother needs P_{t+1|t}^{-1}
 // in eqn11. Both are applied through the lower Cholesky factor L and its
 // inverse Li = L^{-1}: S^{-1} B = Li^T (Li B), and the smoother gain
 // A_t = P_{t|t} P_{t+1|t}^{-1} = (Li P_{t|t})^T Li. Li is obtained by solving
-// L Z = I in the same right-looking sweep as the factorisation, so every
-// O(n^3) part is a large MFMA product:
+// L Z = I in the same right-looking sweep as the factorisation.
 //
-//   for each 64-column block k:
-//     1. one workgroup factors the diagonal block in LDS and inverts it
-//        (L_kk, Li_kk), flagging a non-positive or non-finite pivot;
-//     2. panel:    L_{>k,k} = A_{>k,k} Li_kk^T        and  Z_{k,<k} = Li_kk Z_{k,<k}
-//     3. trailing: A_{>k,>k} -= L_{>k,k} L_{>k,k}^T   and  Z_{>k,<=k} -= L_{>k,k} Z_{k,<=k}
-//   (2 and 3 are each one grouped GEMM launch.)
+// Two-level blocking keeps the O(n^3) work in large MFMA products with a long
+// K dimension:
+//   for each 256-column panel K:
+//     for each 64-column block k of the panel:
+//       1. one workgroup per matrix factors the diagonal block in LDS and inverts
+//          it (L_kk, Li_kk), flagging a non-positive or non-finite pivot;
+//       2. L_{>k,k} = A_{>k,k} Li_kk^T  and  Z_{k,<k} = Li_kk Z_{k,<k}
+//       3. inside the panel only: A_{>k,(k,K]} -= L_{>k,k} L_{(k,K],k}^T and
+//          Z_{(k,K],<=k} -= L_{(k,K],k} Z_{k,<=k}
+//     4. trailing, K = 256:  A_{>K,>K} -= L_{>K,K} L_{>K,K}^T  and
+//        Z_{>K,<=K} -= L_{>K,K} Z_{K,<=K}
+// Steps 2-4 are each one grouped GEMM launch over the whole batch, so the
+// latency of the sequential sweep is shared by every matrix of the batch.
 #include "kf_internal.h"
 
 namespace kfmeg {
 
 namespace {
 
-constexpr int NB = 64;
+constexpr int NB = 64;      // diagonal block
+constexpr int NB2 = 256;    // panel (K of the trailing update)
 constexpr int NTD = 256;
 
-__global__ __launch_bounds__(NTD) void potrf_inv_diag(double* W, int64_t ldw, double* Z, int64_t ldz, int nb,
-                                                      int* status, int which, int step, int row0) {
-    __shared__ double A[NB][NB + 1];
-    __shared__ double Zs[NB][NB + 1];
-    __shared__ double Ld[NB];
-    __shared__ int bad;
+struct DiagBatch {
+    double* W[kMaxBatch];
+    double* Z[kMaxBatch];
+    int step[kMaxBatch];
+};
+
+// One workgroup per matrix factors a diagonal block of at most NB columns (rows past
+// nb are padded with the identity) and inverts the factor, in registers.
+//
+// Thread t owns column c = t % 64 at rows g, g+4, ..., g+60 (g = t / 64) of both the
+// matrix being factored (a) and U, the inverse of its factor with the row scaling
+// deferred (L^{-1}[i][c] = U[i][c] / L[i][i], U starts as the identity). Step j
+// publishes column j below the pivot d_j (colbuf, zero at and above it) and row j
+// of U through LDS, double buffered so that one barrier per step suffices; then
+//     a[i] -= colbuf[i] colbuf[c] / d_j   (c > j: the Schur complement)
+//     u[i] -= colbuf[i] U[j][c] / d_j     (c <= j: forward substitution)
+// one FMA each. Column j of L (colbuf / sqrt(d_j)) is collected in LDS and written
+// out at the end. 1/sqrt(d_j) comes from the hardware estimate refined by two
+// Newton steps (accurate to a few ulp).
+__global__ __launch_bounds__(NTD) void potrf_inv_diag(DiagBatch B, int64_t ldw, int64_t ldz, int nb, int* status,
+                                                      int which, int row0) {
+    __shared__ double colbuf[2][NB];
+    __shared__ double urow[2][NB];
+    __shared__ double piv[2];
+    __shared__ double invs[NB];
+    __shared__ double Ls[NB][NB + 1];
+    double* W = B.W[blockIdx.x];
+    double* Z = B.Z[blockIdx.x];
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < NB * NB; idx += NTD) {
-        const int i = idx / NB, c = idx - i * NB;
-        A[i][c] = (i < nb && c <= i) ? W[(int64_t)i * ldw + c] : 0.0;
-        Zs[i][c] = (i == c) ? 1.0 : 0.0;
+    const int c = tid & (NB - 1), g = tid >> 6;
+    double a[NB / 4], u[NB / 4];
+#pragma unroll
+    for (int r = 0; r < NB / 4; ++r) {
+        const int i = g + 4 * r;
+        a[r] = (i < nb && c <= i) ? W[(int64_t)i * ldw + c] : (i == c ? 1.0 : 0.0);
+        u[r] = i == c ? 1.0 : 0.0;
     }
-    if (tid == 0) bad = -1;
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        const double d = A[j][j];
+    int bad = -1;
+#pragma unroll 1
+    for (int j = 0; j < NB; ++j) {
+        const int buf = j & 1, rj = j >> 2;
+        if (c == j) {
+#pragma unroll
+            for (int r = 0; r < NB / 4; ++r) colbuf[buf][g + 4 * r] = (g + 4 * r > j) ? a[r] : 0.0;
+            if (g == (j & 3)) piv[buf] = a[rj];
+        }
+        if (g == (j & 3)) urow[buf][c] = u[rj];
+        __syncthreads();
+        const double d = piv[buf];
         if (!(d > 0.0) || !isfinite(d)) {       // same value in every thread: uniform exit
-            if (tid == 0) bad = j;
+            bad = j;
             break;
         }
-        const double sq = sqrt(d), inv = 1.0 / sq;
-        for (int i = j + 1 + tid; i < nb; i += NTD) A[i][j] *= inv;
-        for (int c = tid; c <= j; c += NTD) Zs[j][c] *= inv;
-        if (tid == 0) Ld[j] = sq;
-        __syncthreads();
-        const int rows = nb - j - 1;
-        for (int idx = tid; idx < rows * nb; idx += NTD) {
-            const int i = j + 1 + idx / nb, c = idx % nb;
-            const double lij = A[i][j];
-            if (c <= j) Zs[i][c] -= lij * Zs[j][c];
-            else if (c <= i) A[i][c] -= lij * A[c][j];
+        double y = __builtin_amdgcn_rsq(d);
+        y = y * (1.5 - 0.5 * d * y * y);
+        y = y * (1.5 - 0.5 * d * y * y);
+        const double inv2 = y * y;
+        const double ma = c > j ? colbuf[buf][c] * inv2 : 0.0;
+        const double mu = c <= j ? urow[buf][c] * inv2 : 0.0;
+#pragma unroll
+        for (int r = 0; r < NB / 4; ++r) {
+            const double cb = colbuf[buf][g + 4 * r];
+            a[r] = fma(-cb, ma, a[r]);
+            u[r] = fma(-cb, mu, u[r]);
         }
-        __syncthreads();
+        if (g == 0) Ls[c][j] = c > j ? colbuf[buf][c] * y : (c == j ? d * y : 0.0);
+        if (tid == 0) invs[j] = y;
     }
     __syncthreads();
-    for (int idx = tid; idx < nb * nb; idx += NTD) {
-        const int i = idx / nb, c = idx - i * nb;
-        W[(int64_t)i * ldw + c] = c < i ? A[i][c] : (c == i ? Ld[i] : 0.0);
-        Z[(int64_t)i * ldz + c] = c <= i ? Zs[i][c] : 0.0;
+#pragma unroll
+    for (int r = 0; r < NB / 4; ++r) {
+        const int i = g + 4 * r;
+        if (i < nb && c < nb) {
+            W[(int64_t)i * ldw + c] = c <= i ? Ls[i][c] : 0.0;
+            Z[(int64_t)i * ldz + c] = c <= i ? u[r] * invs[i] : 0.0;
+        }
     }
-    if (tid == 0 && bad >= 0 && status) {
+    if (tid == 0 && bad >= 0 && bad < nb && status) {
         if (atomicCAS(&status[0], 0, 1) == 0) {
             status[1] = which;
-            status[2] = step;
+            status[2] = B.step[blockIdx.x];
             status[3] = row0 + bad;
         }
     }
@@ -73,59 +118,101 @@ __global__ __launch_bounds__(NTD) void potrf_inv_diag(double* W, int64_t ldw, do
 
 }  // namespace
 
-hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, int* status, int which, int step,
-                    hipStream_t s) {
-    hipError_t e = zero2d(n, n, Z, ldz, s);
-    if (e != hipSuccess) return e;
-    for (int k0 = 0; k0 < n; k0 += NB) {
-        const int kb = n - k0 < NB ? n - k0 : NB;
-        const int r0 = k0 + kb, rem = n - r0;
-        double* Wkk = W + (int64_t)k0 * ldw + k0;
-        double* Zkk = Z + (int64_t)k0 * ldz + k0;
-        hipLaunchKernelGGL(potrf_inv_diag, dim3(1), dim3(NTD), 0, s, Wkk, ldw, Zkk, ldz, kb, status, which, step,
-                           k0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z, int64_t ldz, int count,
+                          int* status, int which, const int* steps, hipStream_t s) {
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    hipError_t e;
+    for (int b = 0; b < count; ++b)
+        if ((e = zero2d(n, n, Z[b], ldz, s)) != hipSuccess) return e;
+    auto w = [&](int b, int i, int j) { return W[b] + (int64_t)i * ldw + j; };
+    auto z = [&](int b, int i, int j) { return Z[b] + (int64_t)i * ldz + j; };
+    for (int c0 = 0; c0 < n; c0 += NB2) {
+        const int r2 = c0 + (n - c0 < NB2 ? n - c0 : NB2);
+        for (int k0 = c0; k0 < r2; k0 += NB) {
+            const int kb = r2 - k0 < NB ? r2 - k0 : NB;
+            const int r = k0 + kb;
+            DiagBatch db;
+            for (int b = 0; b < count; ++b) {
+                db.W[b] = w(b, k0, k0);
+                db.Z[b] = z(b, k0, k0);
+                db.step[b] = steps ? steps[b] : 0;
+            }
+            hipLaunchKernelGGL(potrf_inv_diag, dim3(count), dim3(NTD), 0, s, db, ldw, ldz, kb, status, which, k0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
 
-        GemmProblem pr[2];
-        int np = 0;
-        if (rem > 0) {                    // L_{>k,k} = A_{>k,k} Li_kk^T   (in place)
-            GemmProblem p;
-            p.M = rem; p.N = kb; p.K = kb;
-            p.A = W + (int64_t)r0 * ldw + k0; p.lda = ldw;
-            p.B = Zkk; p.ldb = ldz; p.flags = G_TB | G_BUPPER;
-            p.C = W + (int64_t)r0 * ldw + k0; p.ldc = ldw;
-            pr[np++] = p;
+            GemmProblem pr[kMaxGroup];
+            int np = 0;
+            for (int b = 0; b < count; ++b) {
+                if (r < n) {              // L_{>k,k} = A_{>k,k} Li_kk^T   (in place, one column tile)
+                    GemmProblem p;
+                    p.M = n - r; p.N = kb; p.K = kb;
+                    p.A = w(b, r, k0); p.lda = ldw;
+                    p.B = z(b, k0, k0); p.ldb = ldz; p.flags = G_TB | G_BUPPER;
+                    p.C = w(b, r, k0); p.ldc = ldw;
+                    pr[np++] = p;
+                }
+                if (k0 > 0) {             // Z_{k,<k} = Li_kk Z_{k,<k}   (in place, one row tile)
+                    GemmProblem p;
+                    p.M = kb; p.N = k0; p.K = kb;
+                    p.A = z(b, k0, k0); p.lda = ldz; p.flags = G_ALOWER;
+                    p.B = z(b, k0, 0); p.ldb = ldz;
+                    p.C = z(b, k0, 0); p.ldc = ldz;
+                    pr[np++] = p;
+                }
+            }
+            if (np && (e = gemm_launch(Dt::F64, pr, np, s)) != hipSuccess) return e;
+            if (r < r2) {                 // updates inside the panel
+                np = 0;
+                for (int b = 0; b < count; ++b) {
+                    GemmProblem t1, t2;
+                    t1.M = n - r; t1.N = r2 - r; t1.K = kb;
+                    t1.A = w(b, r, k0); t1.lda = ldw;
+                    t1.B = w(b, r, k0); t1.ldb = ldw; t1.flags = G_TB;
+                    t1.alpha = -1.0; t1.beta = 1.0;
+                    t1.Cin = w(b, r, r); t1.ldcin = ldw;
+                    t1.C = w(b, r, r); t1.ldc = ldw;
+                    t2.M = r2 - r; t2.N = r; t2.K = kb;
+                    t2.A = w(b, r, k0); t2.lda = ldw;
+                    t2.B = z(b, k0, 0); t2.ldb = ldz;
+                    t2.alpha = -1.0; t2.beta = 1.0;
+                    t2.Cin = z(b, r, 0); t2.ldcin = ldz;
+                    t2.C = z(b, r, 0); t2.ldc = ldz;
+                    pr[np++] = t1;
+                    pr[np++] = t2;
+                }
+                if ((e = gemm_launch(Dt::F64, pr, np, s)) != hipSuccess) return e;
+            }
         }
-        if (k0 > 0) {                     // Z_{k,<k} = Li_kk Z_{k,<k}   (in place)
-            GemmProblem p;
-            p.M = kb; p.N = k0; p.K = kb;
-            p.A = Zkk; p.lda = ldz; p.flags = G_ALOWER;
-            p.B = Z + (int64_t)k0 * ldz; p.ldb = ldz;
-            p.C = Z + (int64_t)k0 * ldz; p.ldc = ldz;
-            pr[np++] = p;
-        }
-        if (np && (e = gemm_launch(Dt::F64, pr, np, s)) != hipSuccess) return e;
-        if (rem > 0) {
-            GemmProblem t1, t2;           // trailing Schur complement and right-hand side
-            t1.M = rem; t1.N = rem; t1.K = kb;
-            t1.A = W + (int64_t)r0 * ldw + k0; t1.lda = ldw;
-            t1.B = W + (int64_t)r0 * ldw + k0; t1.ldb = ldw;
-            t1.flags = G_TB | G_LOWER;
-            t1.alpha = -1.0; t1.beta = 1.0;
-            t1.Cin = W + (int64_t)r0 * ldw + r0; t1.ldcin = ldw;
-            t1.C = W + (int64_t)r0 * ldw + r0; t1.ldc = ldw;
-
-            t2.M = rem; t2.N = r0; t2.K = kb;
-            t2.A = W + (int64_t)r0 * ldw + k0; t2.lda = ldw;
-            t2.B = Z + (int64_t)k0 * ldz; t2.ldb = ldz;
-            t2.alpha = -1.0; t2.beta = 1.0;
-            t2.Cin = Z + (int64_t)r0 * ldz; t2.ldcin = ldz;
-            t2.C = Z + (int64_t)r0 * ldz; t2.ldc = ldz;
-            GemmProblem tr[2] = {t1, t2};
-            if ((e = gemm_launch(Dt::F64, tr, 2, s)) != hipSuccess) return e;
+        if (r2 < n) {                     // trailing update with K = the panel width
+            GemmProblem pr[kMaxGroup];
+            int np = 0;
+            for (int b = 0; b < count; ++b) {
+                GemmProblem t1, t2;
+                t1.M = n - r2; t1.N = n - r2; t1.K = r2 - c0;
+                t1.A = w(b, r2, c0); t1.lda = ldw;
+                t1.B = w(b, r2, c0); t1.ldb = ldw;
+                t1.flags = G_TB | G_LOWER;
+                t1.alpha = -1.0; t1.beta = 1.0;
+                t1.Cin = w(b, r2, r2); t1.ldcin = ldw;
+                t1.C = w(b, r2, r2); t1.ldc = ldw;
+                t2.M = n - r2; t2.N = r2; t2.K = r2 - c0;
+                t2.A = w(b, r2, c0); t2.lda = ldw;
+                t2.B = z(b, c0, 0); t2.ldb = ldz;
+                t2.alpha = -1.0; t2.beta = 1.0;
+                t2.Cin = z(b, r2, 0); t2.ldcin = ldz;
+                t2.C = z(b, r2, 0); t2.ldc = ldz;
+                pr[np++] = t1;
+                pr[np++] = t2;
+            }
+            if ((e = gemm_launch(Dt::F64, pr, np, s)) != hipSuccess) return e;
         }
     }
     return hipSuccess;
+}
+
+hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, int* status, int which, int step,
+                    hipStream_t s) {
+    return chol_inv_batch(n, &W, ldw, &Z, ldz, 1, status, which, &step, s);
 }
 
 }  // namespace kfmeg

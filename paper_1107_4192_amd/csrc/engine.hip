@@ -42,14 +42,13 @@ struct kf_plan {
 
     // model
     double *X = nullptr, *Q = nullptr, *R = nullptr, *x0 = nullptr, *P0 = nullptr;
-    float *X32 = nullptr, *Q32 = nullptr, *P032 = nullptr;
+    double* XQ = nullptr;                   // X Q (m x N): X (P + Q) = X P + X Q
     // filter workspace
     double *Bm = nullptr, *Cm = nullptr, *S = nullptr, *Lis = nullptr, *e = nullptr, *w = nullptr, *xw = nullptr;
     float* Cm32 = nullptr;
     double* partial = nullptr;
     size_t partial_elems = 0;
     double* Pw[2] = {nullptr, nullptr};     // float64 working pair (store in float32 or checkpointed)
-    float* P32w = nullptr;                  // float32 copy of P_{t|t} (mixed, float64 store)
     // covariance store
     bool store32 = false;
     int stride = 1;                         // keep slots t with (t+1) % stride == 0 and t = T-1
@@ -58,8 +57,19 @@ struct kf_plan {
     // segment buffer for recomputation (checkpointed mode)
     void* seg = nullptr;
     // smoother workspace
-    double *W = nullptr, *Li = nullptr, *Ab = nullptr, *Ps[2] = {nullptr, nullptr}, *Pt64 = nullptr;
-    float *A32 = nullptr, *D32 = nullptr, *M32 = nullptr;
+    // Smoother gains are formed for up to `gbatch` time steps at once (they are independent
+    // given the stored P_{t|t}) on a second stream, one batch ahead of the back-recursion;
+    // the gains, and the upcast P_{t|t} they came from, are double buffered (set 0 / 1).
+    int gbatch = 1;
+    double *W[kMaxBatch] = {}, *Li[kMaxBatch] = {};
+    double* Ab[2][kMaxBatch] = {};
+    double* Pt64[2][kMaxBatch] = {};
+    float* A32[2][kMaxBatch] = {};
+    double* Ps[2] = {nullptr, nullptr};
+    double *Dm = nullptr, *Mm = nullptr;    // D = P_{t+1|T} - P_{t+1|t} and M = A_t D (float64 path)
+    float *D32 = nullptr, *M32 = nullptr;   // the same in float32 (mixed path)
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_start = nullptr, ev_gain[2] = {nullptr, nullptr}, ev_chain[2] = {nullptr, nullptr};
     // status
     int* dstatus = nullptr;
     int* hstatus = nullptr;
@@ -137,15 +147,17 @@ size_t store_bytes(int64_t N, int64_t ldN, int64_t T, bool s32, int stride) {
     return (size_t)slots_needed(T, stride) * (size_t)N * ldN * (s32 ? 4 : 8);
 }
 
-size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride) {
+size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int gb) {
     const int64_t ldN = round_up(N, 16), ldm = round_up(m, 16);
     const size_t NN = (size_t)N * ldN;
     size_t b = 0;
-    b += 8 * (2 * NN + (size_t)m * ldN + (size_t)m * ldm + 2 * (size_t)N);   // Q, P0, X, R, x0
+    b += 8 * (2 * NN + 2 * (size_t)m * ldN + (size_t)m * ldm + 2 * (size_t)N);   // Q, P0, X, XQ, R, x0
     b += 8 * (2 * (size_t)m * ldN + 2 * (size_t)m * ldm + 3 * (size_t)N + 64);
     b += 8 * (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);                 // split-K partials
-    b += 8 * 5 * NN;                                                             // W, Li, A, Ps x2
-    if (mix) b += 4 * (3 * NN + (size_t)m * ldN + (size_t)m * ldN + NN) + 8 * NN;
+    b += 8 * (4 * (size_t)gb + 2) * NN;                                          // W, Li, 2 x A per batch; Ps x2
+    if (!mix) b += 8 * 2 * NN;                                                   // D, M
+    if (s32) b += 8 * 2 * (size_t)gb * NN;                                       // upcast P_{t|t}
+    if (mix) b += 4 * (2 * (size_t)gb * NN + 2 * NN + (size_t)m * ldN);     // A32, D32, M32, Cm32
     if (s32 || stride > 1) b += 8 * 2 * NN;
     if (mix) b += 4 * NN;
     if (stride > 1) b += (size_t)stride * NN * (s32 ? 4 : 8);
@@ -165,28 +177,24 @@ kf_status status_check(kf_plan* p, const char* phase) {
     return KF_OK;
 }
 
-// One covariance step of the filter from P_prev (index t-1, or P0) to P_t; with `x`/`y`, also the mean.
-// Pprev64/32: float64 / float32 views of P_{t-1|t-1} (the float32 one only in mixed mode).
-kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, const float* Pprev32, double* Pout64,
+// One covariance step of the filter from P_prev = P_{t-1|t-1} (or P0) to P_t; with `y`, also the mean.
+// Pout32 (optional) receives a float32 copy of P_t.
+kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* Pout64,
                           float* Pout32, double* diag_out, const double* y, double* x_out_row) {
     const int N = (int)p->N, m = (int)p->m;
     hipStream_t s = p->stream;
-    // B = X (P_prev + Q)
+    // B = X (P_prev + Q) = X P_prev + X Q, in float64 in both precisions: the gain and the
+    // mean depend on it through S^{-1}, where rounding is amplified by cond(S).
     {
         GemmProblem g;
         g.M = m; g.N = N; g.K = N;
         g.ksplit = 4;
         g.partial = p->partial;
+        g.Cin = p->XQ; g.ldcin = p->ldN; g.beta = 1.0;
         g.C = p->Bm; g.ldc = p->ldN;
-        if (mixed(p)) {
-            g.A = p->X32; g.lda = p->ldN;
-            g.B = Pprev32; g.ldb = p->ldN; g.B2 = p->Q32; g.ldb2 = p->ldN; g.b2coef = 1.0;
-            HIPCK(gemm1(Dt::F32, g, s));
-        } else {
-            g.A = p->X; g.lda = p->ldN;
-            g.B = Pprev64; g.ldb = p->ldN; g.B2 = p->Q; g.ldb2 = p->ldN; g.b2coef = 1.0;
-            HIPCK(gemm1(Dt::F64, g, s));
-        }
+        g.A = p->X; g.lda = p->ldN;
+        g.B = Pprev64; g.ldb = p->ldN; g.flags = G_TB;   // P symmetric: read row-contiguous
+        HIPCK(gemm1(Dt::F64, g, s));
     }
     // S = B X^T + R
     {
@@ -244,24 +252,28 @@ kf_status sync_and_check(kf_plan* p, const char* phase) {
     return status_check(p, phase);
 }
 
-// Launch one of the smoother's N x N x N products (named instantiation), timed when profiling.
-kf_status big_gemm(kf_plan* p, Dt dt, GemmProblem g, double flops) {
-    g.flags |= G_NXN;
+// Launch a group of the smoother's N x N x N products (named instantiation), timed when profiling.
+kf_status big_group(kf_plan* p, Dt dt, GemmProblem* g, int count, double flops, hipStream_t st) {
+    for (int u = 0; u < count; ++u) g[u].flags |= G_NXN;
     if (p->prof) {
         while (p->ev.size() < p->ev_used + 2) {
             hipEvent_t e;
             HIPCK(hipEventCreate(&e));
             p->ev.push_back(e);
         }
-        HIPCK(hipEventRecord(p->ev[p->ev_used], p->stream));
+        HIPCK(hipEventRecord(p->ev[p->ev_used], st));
     }
-    HIPCK(gemm1(dt, g, p->stream));
+    HIPCK(gemm_launch(dt, g, count, st));
     if (p->prof) {
-        HIPCK(hipEventRecord(p->ev[p->ev_used + 1], p->stream));
+        HIPCK(hipEventRecord(p->ev[p->ev_used + 1], st));
         p->ev_flops.push_back(flops);
         p->ev_used += 2;
     }
     return KF_OK;
+}
+
+kf_status big_gemm(kf_plan* p, Dt dt, GemmProblem g, double flops, hipStream_t st) {
+    return big_group(p, dt, &g, 1, flops, st);
 }
 
 // After the stream has been synchronised: fold the recorded event pairs into the totals.
@@ -297,7 +309,7 @@ size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt) {
     if (N <= 0 || m <= 0 || T <= 0) return 0;
     const int64_t ldN = round_up(N, 16);
     const int stride = o.checkpoint_stride > 0 ? o.checkpoint_stride : 1;
-    return workspace_bytes(N, m, o.precision == KF_MIXED, o.store_fp32, stride) +
+    return workspace_bytes(N, m, o.precision == KF_MIXED, o.store_fp32, stride, kMaxBatch) +
            store_bytes(N, ldN, T, o.store_fp32, stride);
 }
 
@@ -335,19 +347,22 @@ kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const do
     }
     int stride = p->opt.checkpoint_stride > 0 ? p->opt.checkpoint_stride : 1;
     const bool mix = mixed(p);
+    auto need = [&](int st, int gb) {
+        return workspace_bytes(N, m, mix, p->store32, st, gb) + store_bytes(N, p->ldN, T_max, p->store32, st);
+    };
+    // Prefer storing every P_{t|t}; give up gain batching before checkpointing.
+    int gb = kMaxBatch;
+    while (gb > 1 && need(stride, gb) > budget) gb /= 2;
     if (p->opt.checkpoint_stride <= 0) {
-        while (stride < T_max &&
-               workspace_bytes(N, m, mix, p->store32, stride) + store_bytes(N, p->ldN, T_max, p->store32, stride) >
-                   budget) {
+        while (stride < T_max && need(stride, gb) > budget)
             stride = stride == 1 ? std::max<int>(2, (int)std::ceil(std::sqrt((double)T_max))) : stride + 1;
-        }
     }
-    if (workspace_bytes(N, m, mix, p->store32, stride) + store_bytes(N, p->ldN, T_max, p->store32, stride) >
-        budget) {
+    if (need(stride, gb) > budget) {
         g_err = "kf_create: the covariance store does not fit the HBM budget even with checkpointing";
         delete p;
         return KF_ENOMEM;
     }
+    p->gbatch = gb;
     p->stride = stride;
     p->nslots = slots_needed(T_max, stride);
 
@@ -361,17 +376,25 @@ kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const do
     const size_t mN = (size_t)m * p->ldN, mm = (size_t)m * p->ldm;
 #define ALLOC(ptr, n)                        \
     if ((st = alloc(p, &(ptr), (n))) != KF_OK) return fail(st);
-    ALLOC(p->X, mN); ALLOC(p->Q, NN); ALLOC(p->R, mm); ALLOC(p->x0, (size_t)N); ALLOC(p->P0, NN);
+    ALLOC(p->X, mN); ALLOC(p->XQ, mN); ALLOC(p->Q, NN); ALLOC(p->R, mm); ALLOC(p->x0, (size_t)N); ALLOC(p->P0, NN);
     ALLOC(p->Bm, mN); ALLOC(p->Cm, mN); ALLOC(p->S, mm); ALLOC(p->Lis, mm);
     ALLOC(p->e, (size_t)m); ALLOC(p->w, (size_t)m); ALLOC(p->xw, (size_t)N);
     p->partial_elems = (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);
     ALLOC(p->partial, p->partial_elems);
     ALLOC(p->dstatus, 4);
-    ALLOC(p->W, NN); ALLOC(p->Li, NN); ALLOC(p->Ab, NN); ALLOC(p->Ps[0], NN); ALLOC(p->Ps[1], NN);
+    for (int b = 0; b < p->gbatch; ++b) {
+        ALLOC(p->W[b], NN); ALLOC(p->Li[b], NN);
+        for (int set = 0; set < 2; ++set) {
+            ALLOC(p->Ab[set][b], NN);
+            if (p->store32) ALLOC(p->Pt64[set][b], NN);
+            if (mix) ALLOC(p->A32[set][b], NN);
+        }
+    }
+    ALLOC(p->Ps[0], NN); ALLOC(p->Ps[1], NN);
+    if (!mix) { ALLOC(p->Dm, NN); ALLOC(p->Mm, NN); }
     if (mix) {
-        ALLOC(p->X32, mN); ALLOC(p->Q32, NN); ALLOC(p->P032, NN); ALLOC(p->Cm32, mN);
-        ALLOC(p->A32, NN); ALLOC(p->D32, NN); ALLOC(p->M32, NN); ALLOC(p->Pt64, NN);
-        ALLOC(p->P32w, NN);
+        ALLOC(p->Cm32, mN);
+        ALLOC(p->D32, NN); ALLOC(p->M32, NN);
     }
     if (p->store32 || stride > 1) { ALLOC(p->Pw[0], NN); ALLOC(p->Pw[1], NN); }
     {
@@ -399,6 +422,15 @@ kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const do
         p->err = "pinned host allocation failed";
         return fail(KF_ENOMEM);
     }
+    if (hipStreamCreateWithFlags(&p->s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_gain[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_gain[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_chain[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_chain[1], hipEventDisableTiming) != hipSuccess) {
+        p->err = "kf_create: creating the side stream or its events failed";
+        return fail(KF_EHIP);
+    }
     hipStream_t s = p->stream;
     auto cp = [&](void* dst, bool d32, int64_t ldd, const double* src, int64_t rows, int64_t cols) {
         return copy2d((int)rows, (int)cols, dst, d32, ldd, src, false, cols, s);
@@ -409,10 +441,13 @@ kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const do
         p->err = "kf_create: copying the model failed";
         return fail(KF_EHIP);
     }
-    if (mix) {
-        if (cp(p->X32, true, p->ldN, X, m, N) != hipSuccess || cp(p->Q32, true, p->ldN, Q, N, N) != hipSuccess ||
-            cp(p->P032, true, p->ldN, P0, N, N) != hipSuccess) {
-            p->err = "kf_create: copying the model failed";
+    {
+        GemmProblem g;                           // X Q, used by every filter step
+        g.M = (int)m; g.N = (int)N; g.K = (int)N;
+        g.A = p->X; g.lda = p->ldN; g.B = p->Q; g.ldb = p->ldN;
+        g.C = p->XQ; g.ldc = p->ldN;
+        if (gemm1(Dt::F64, g, s) != hipSuccess) {
+            p->err = "kf_create: forming X Q failed";
             return fail(KF_EHIP);
         }
     }
@@ -438,20 +473,17 @@ static kf_status filter_impl(kf_plan* p, int64_t T, const double* Y, double* x_f
     HIPCK(hipMemcpyAsync(p->xw, p->x0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     const bool direct = !p->store32 && p->stride == 1;   // store slot t is the working P
     const double* prev64 = p->P0;
-    const float* prev32 = p->P032;
     for (int64_t t = 0; t < T; ++t) {
         double* out64 = direct ? static_cast<double*>(slot_ptr(p, t)) : p->Pw[t & 1];
         float* out32 = nullptr;
         if (p->store32 && kept(p, t, T)) out32 = static_cast<float*>(slot_ptr(p, slot_of(p, t, T)));
-        else if (mixed(p)) out32 = p->P32w;     // float32 operand of the next step's product
-        TRY(filter_cov_step(p, t, prev64, prev32, out64, out32, Pdiag ? Pdiag + t * N : nullptr, Y + t * m,
+        TRY(filter_cov_step(p, t, prev64, out64, out32, Pdiag ? Pdiag + t * N : nullptr, Y + t * m,
                             x_filt + t * N));
         if (!direct && !p->store32 && kept(p, t, T)) {
             HIPCK(hipMemcpyAsync(slot_ptr(p, slot_of(p, t, T)), out64, slot_elems(p) * 8, hipMemcpyDeviceToDevice,
                                  s));
         }
         prev64 = out64;
-        prev32 = out32;
     }
     return sync_and_check(p, "kf_filter");
 }
@@ -484,101 +516,104 @@ kf_status recompute_segment(kf_plan* p, int64_t t0, int64_t t1, int64_t T) {
     const size_t esz = s32 ? 4 : 8;
     // starting covariance: P_{t0-1} from its checkpoint (or P0)
     const double* prev64;
-    const float* prev32 = nullptr;
     if (t0 == 0) {
         prev64 = p->P0;
-        prev32 = p->P032;
     } else {
         const void* src = slot_ptr(p, slot_of(p, t0 - 1, T));
         HIPCK(copy2d((int)p->N, (int)p->N, p->Pw[0], false, p->ldN, src, s32, p->ldN, s));
         prev64 = p->Pw[0];
-        if (mixed(p)) {
-            if (s32) prev32 = static_cast<const float*>(src);
-            else {
-                HIPCK(copy2d((int)p->N, (int)p->N, p->P32w, true, p->ldN, src, false, p->ldN, s));
-                prev32 = p->P32w;
-            }
-        }
     }
     for (int64_t t = t0; t <= t1; ++t) {
         double* out64 = p->Pw[(t - t0 + 1) & 1];
         void* segslot = static_cast<char*>(p->seg) + (size_t)(t - t0) * slot_elems(p) * esz;
-        float* out32 = s32 ? static_cast<float*>(segslot) : (mixed(p) ? p->P32w : nullptr);
-        TRY(filter_cov_step(p, t, prev64, prev32, out64, out32, nullptr, nullptr, nullptr));
+        float* out32 = s32 ? static_cast<float*>(segslot) : nullptr;
+        TRY(filter_cov_step(p, t, prev64, out64, out32, nullptr, nullptr, nullptr));
         if (!s32) HIPCK(hipMemcpyAsync(segslot, out64, slot_elems(p) * 8, hipMemcpyDeviceToDevice, s));
         prev64 = out64;
-        prev32 = out32;
     }
     return KF_OK;
 }
 
-// One smoother step t (0-based, t <= T-2). Pt: stored P_{t|t} (float32 or float64).
-kf_status smooth_step(kf_plan* p, int64_t t, const void* Pt, const double* Ps_next, double* Ps_out,
-                      const double* xf, double* xs, double* Pdiag) {
+// Smoother gains for a batch of steps (eqn11): A_t = P_{t|t} P_{t+1|t}^{-1} for each
+// t = ts[b], formed as G = Li P_t, A_t = G^T Li with L Li = chol(P_t + Q), into gain set
+// `set`. The steps are independent given the stored P_{t|t}, so every launch covers the
+// whole batch.
+kf_status gain_batch(kf_plan* p, int set, int count, const int64_t* ts, const void* const* Pt, hipStream_t s) {
+    const int N = (int)p->N;
+    const int64_t ld = p->ldN;
+    const double* P64[kMaxBatch];
+    int steps[kMaxBatch];
+    for (int b = 0; b < count; ++b) {
+        P64[b] = static_cast<const double*>(Pt[b]);
+        if (p->store32) {
+            HIPCK(copy2d(N, N, p->Pt64[set][b], false, ld, Pt[b], true, ld, s));
+            P64[b] = p->Pt64[set][b];
+        }
+        // W = P_t + Q  (= P_{t+1|t}, eqn7)
+        HIPCK(axpby3(N, N, p->W[b], false, ld, P64[b], false, ld, p->Q, false, ld, 1.0, nullptr, false, 0, 0.0, s));
+        steps[b] = (int)ts[b] + 1;
+    }
+    HIPCK(chol_inv_batch(N, p->W, ld, p->Li, ld, count, p->dstatus, W_PPRED, steps, s));
+    // A_t = P_t Li^T Li. H = P_t Li^T goes into W (L is not needed any more); Li is then
+    // transposed in place so that both products read their second operand row-contiguous.
+    GemmProblem g[kMaxBatch], h[kMaxBatch];
+    for (int b = 0; b < count; ++b) {
+        g[b].M = N; g[b].N = N; g[b].K = N;    // H = P_t Li^T   (B(l,k) = Li[k][l], zero for l > k)
+        g[b].A = P64[b]; g[b].lda = ld;
+        g[b].B = p->Li[b]; g[b].ldb = ld; g[b].flags = G_TB | G_BUPPER;
+        g[b].C = p->W[b]; g[b].ldc = ld;
+        h[b].M = N; h[b].N = N; h[b].K = N;    // A_t = H Li     (B(k,j) = Li[k][j] = LiT[j][k])
+        h[b].A = p->W[b]; h[b].lda = ld;
+        h[b].B = p->Li[b]; h[b].ldb = ld; h[b].flags = G_TB | G_BLOWER;
+        h[b].C = p->Ab[set][b]; h[b].ldc = ld;
+        if (mixed(p)) { h[b].C32 = p->A32[set][b]; h[b].ldc32 = ld; }
+    }
+    TRY(big_group(p, Dt::F64, g, count, (double)count * N * N * N, s));
+    for (int b = 0; b < count; ++b) HIPCK(transpose_inplace(p->Li[b], ld, N, s));
+    TRY(big_group(p, Dt::F64, h, count, (double)count * N * N * N, s));
+    return KF_OK;
+}
+
+// The sequential part of smoother step t given A_t (slot b of gain set `set`):
+// eqn12 for the mean and eqn13 for the covariance.
+kf_status chain_step(kf_plan* p, int set, int b, int64_t t, const void* Pt, const double* Ps_next,
+                     double* Ps_out, const double* xf, double* xs, double* Pdiag) {
     hipStream_t s = p->stream;
     const int N = (int)p->N;
     const int64_t ld = p->ldN;
-    const bool s32 = p->store32;
-    const double* Pt64 = static_cast<const double*>(Pt);
-    if (s32 || mixed(p)) {
-        if (s32) {
-            HIPCK(copy2d(N, N, p->Pt64 ? p->Pt64 : p->Pw[0], false, ld, Pt, true, ld, s));
-            Pt64 = p->Pt64 ? p->Pt64 : p->Pw[0];
-        }
-    }
-    // W = P_t + Q  (= P_{t+1|t}, eqn7)
-    HIPCK(axpby3(N, N, p->W, false, ld, Pt64, false, ld, p->Q, false, ld, 1.0, nullptr, false, 0, 0.0, s));
-    HIPCK(chol_inv(p->W, ld, p->Li, ld, N, p->dstatus, W_PPRED, (int)t + 1, s));
-    // G = Li P_t  (into W; L is not needed any more)
-    {
-        GemmProblem g;
-        g.M = N; g.N = N; g.K = N;
-        g.A = p->Li; g.lda = ld; g.flags = G_ALOWER;
-        g.B = Pt64; g.ldb = ld;
-        g.C = p->W; g.ldc = ld;
-        TRY(big_gemm(p, Dt::F64, g, (double)N * N * N));
-    }
-    // A_t = G^T Li  (eqn11)
-    {
-        GemmProblem g;
-        g.M = N; g.N = N; g.K = N;
-        g.A = p->W; g.lda = ld; g.flags = G_TA | G_BLOWER;
-        g.B = p->Li; g.ldb = ld;
-        g.C = p->Ab; g.ldc = ld;
-        if (mixed(p)) { g.C32 = p->A32; g.ldc32 = ld; }
-        TRY(big_gemm(p, Dt::F64, g, (double)N * N * N));
-    }
+    const double* Pt64 = p->store32 ? p->Pt64[set][b] : static_cast<const double*>(Pt);
+    const double* A = p->Ab[set][b];
     // x_{t|T} = x_{t|t} + A_t (x_{t+1|T} - x_{t|t})   (eqn12, RTS reading)
-    HIPCK(gemv_smooth(p->Ab, ld, xf + (int64_t)t * N, xs + (int64_t)(t + 1) * N, xs + (int64_t)t * N, N, s));
+    HIPCK(gemv_smooth(A, ld, xf + t * N, xs + (t + 1) * N, xs + t * N, N, s));
     if (mixed(p)) {
         // D = P_{t+1|T} - P_t - Q in float32; M = A D; P_{t|T} = P_t + M A^T   (eqn13)
         HIPCK(axpby3(N, N, p->D32, true, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
         GemmProblem g;
         g.M = N; g.N = N; g.K = N;
-        g.A = p->A32; g.lda = ld; g.B = p->D32; g.ldb = ld;
+        g.A = p->A32[set][b]; g.lda = ld; g.B = p->D32; g.ldb = ld; g.flags = G_TB;   // D symmetric
         g.C32 = p->M32; g.ldc32 = ld;
-        TRY(big_gemm(p, Dt::F32, g, 2.0 * N * N * N));
+        TRY(big_gemm(p, Dt::F32, g, 2.0 * N * N * N, s));
         GemmProblem h;
         h.M = N; h.N = N; h.K = N;
-        h.A = p->M32; h.lda = ld; h.B = p->A32; h.ldb = ld; h.flags = G_TB | G_LOWER | G_MIRROR;
+        h.A = p->M32; h.lda = ld; h.B = p->A32[set][b]; h.ldb = ld; h.flags = G_TB | G_LOWER | G_MIRROR;
         h.Cin = Pt64; h.ldcin = ld; h.beta = 1.0;
         h.C = Ps_out; h.ldc = ld; h.diag = Pdiag;
-        TRY(big_gemm(p, Dt::F32, h, (double)N * N * N));
+        TRY(big_gemm(p, Dt::F32, h, (double)N * N * N, s));
     } else {
+        // D = P_{t+1|T} - P_t - Q;  M = A_t D;  P_{t|T} = P_t + M A_t^T   (eqn13)
+        HIPCK(axpby3(N, N, p->Dm, false, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
         GemmProblem g;
         g.M = N; g.N = N; g.K = N;
-        g.A = p->Ab; g.lda = ld;
-        g.B = Ps_next; g.ldb = ld;
-        g.B2 = Pt64; g.ldb2 = ld; g.b2coef = -1.0;
-        g.B3 = p->Q; g.ldb3 = ld; g.b3coef = -1.0;
-        g.C = p->W; g.ldc = ld;
-        TRY(big_gemm(p, Dt::F64, g, 2.0 * N * N * N));
+        g.A = A; g.lda = ld;
+        g.B = p->Dm; g.ldb = ld; g.flags = G_TB;   // D symmetric: read row-contiguous
+        g.C = p->Mm; g.ldc = ld;
+        TRY(big_gemm(p, Dt::F64, g, 2.0 * N * N * N, s));
         GemmProblem h;
         h.M = N; h.N = N; h.K = N;
-        h.A = p->W; h.lda = ld; h.B = p->Ab; h.ldb = ld; h.flags = G_TB | G_LOWER | G_MIRROR;
+        h.A = p->Mm; h.lda = ld; h.B = A; h.ldb = ld; h.flags = G_TB | G_LOWER | G_MIRROR;
         h.Cin = Pt64; h.ldcin = ld; h.beta = 1.0;
         h.C = Ps_out; h.ldc = ld; h.diag = Pdiag;
-        TRY(big_gemm(p, Dt::F64, h, (double)N * N * N));
+        TRY(big_gemm(p, Dt::F64, h, (double)N * N * N, s));
     }
     return KF_OK;
 }
@@ -599,25 +634,80 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
     if (Pfull)
         HIPCK(hipMemcpy2DAsync(Pfull + (T - 1) * N * N, N * 8, p->Ps[(T - 1) & 1], ld * 8, N * 8, N,
                                hipMemcpyDeviceToDevice, s));
-    int64_t seg_lo = -1, seg_hi = -2;
-    for (int64_t t = T - 2; t >= 0; --t) {
-        const void* Pt;
-        if (kept(p, t, T)) {
-            Pt = slot_ptr(p, slot_of(p, t, T));
-        } else {
-            if (t < seg_lo || t > seg_hi) {
+    auto run_chain = [&](int set, int count, const int64_t* ts, const void* const* Pt) -> kf_status {
+        for (int b = 0; b < count; ++b) {
+            const int64_t u = ts[b];
+            double* Ps_out = p->Ps[u & 1];
+            TRY(chain_step(p, set, b, u, Pt[b], p->Ps[(u + 1) & 1], Ps_out, xf, xs, Pdiag ? Pdiag + u * N : nullptr));
+            if (Pfull)
+                HIPCK(hipMemcpy2DAsync(Pfull + u * N * N, N * 8, Ps_out, ld * 8, N * 8, N, hipMemcpyDeviceToDevice,
+                                       s));
+        }
+        return KF_OK;
+    };
+    if (p->stride == 1) {
+        // Every P_{t|t} is stored: gains run one batch ahead on the side stream.
+        struct Batch { int count; int64_t ts[kMaxBatch]; const void* Pt[kMaxBatch]; };
+        std::vector<Batch> batches;
+        for (int64_t t = T - 2; t >= 0;) {
+            Batch bt;
+            bt.count = 0;
+            while (bt.count < p->gbatch && t - bt.count >= 0) {
+                bt.ts[bt.count] = t - bt.count;
+                bt.Pt[bt.count] = slot_ptr(p, t - bt.count);
+                ++bt.count;
+            }
+            batches.push_back(bt);
+            t -= bt.count;
+        }
+        HIPCK(hipEventRecord(p->ev_start, s));
+        HIPCK(hipStreamWaitEvent(p->s2, p->ev_start, 0));
+        const size_t nb = batches.size();
+        if (nb > 0) {
+            TRY(gain_batch(p, 0, batches[0].count, batches[0].ts, batches[0].Pt, p->s2));
+            HIPCK(hipEventRecord(p->ev_gain[0], p->s2));
+        }
+        for (size_t k = 0; k < nb; ++k) {
+            if (k + 1 < nb) {
+                const int set = (int)((k + 1) & 1);
+                if (k >= 1) HIPCK(hipStreamWaitEvent(p->s2, p->ev_chain[set], 0));   // chain k-1 released it
+                TRY(gain_batch(p, set, batches[k + 1].count, batches[k + 1].ts, batches[k + 1].Pt, p->s2));
+                HIPCK(hipEventRecord(p->ev_gain[set], p->s2));
+            }
+            const int set = (int)(k & 1);
+            HIPCK(hipStreamWaitEvent(s, p->ev_gain[set], 0));
+            TRY(run_chain(set, batches[k].count, batches[k].ts, batches[k].Pt));
+            HIPCK(hipEventRecord(p->ev_chain[set], s));
+        }
+    } else {
+        // Checkpointed store: segments are recomputed into one buffer, so everything
+        // stays on the plan's stream.
+        int64_t seg_lo = -1, seg_hi = -2;
+        auto stored = [&](int64_t u) -> const void* {
+            if (kept(p, u, T)) return slot_ptr(p, slot_of(p, u, T));
+            if (u < seg_lo || u > seg_hi) return nullptr;
+            return static_cast<char*>(p->seg) + (size_t)(u - seg_lo) * slot_elems(p) * esz;
+        };
+        int64_t t = T - 2;
+        while (t >= 0) {
+            if (!stored(t)) {
                 // segment of non-kept steps containing t: (previous checkpoint, t]
-                const int64_t lo = (t + 1) / p->stride * p->stride;   // first step after the checkpoint
-                seg_lo = lo;
+                seg_lo = (t + 1) / p->stride * p->stride;
                 seg_hi = t;
                 TRY(recompute_segment(p, seg_lo, seg_hi, T));
             }
-            Pt = static_cast<char*>(p->seg) + (size_t)(t - seg_lo) * slot_elems(p) * esz;
+            int64_t ts[kMaxBatch];
+            const void* Pt[kMaxBatch];
+            int count = 0;
+            while (count < p->gbatch && t - count >= 0 && stored(t - count)) {
+                ts[count] = t - count;
+                Pt[count] = stored(t - count);
+                ++count;
+            }
+            TRY(gain_batch(p, 0, count, ts, Pt, s));
+            TRY(run_chain(0, count, ts, Pt));
+            t -= count;
         }
-        double* Ps_out = p->Ps[t & 1];
-        TRY(smooth_step(p, t, Pt, p->Ps[(t + 1) & 1], Ps_out, xf, xs, Pdiag ? Pdiag + t * N : nullptr));
-        if (Pfull)
-            HIPCK(hipMemcpy2DAsync(Pfull + t * N * N, N * 8, Ps_out, ld * 8, N * 8, N, hipMemcpyDeviceToDevice, s));
     }
     kf_status st = sync_and_check(p, "kf_smooth");
     if (st == KF_OK && p->prof) TRY(collect_profile(p));
@@ -692,6 +782,10 @@ void kf_destroy(kf_plan* p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     else (void)hipDeviceSynchronize();
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    if (p->s2) (void)hipStreamSynchronize(p->s2);
+    for (hipEvent_t e : {p->ev_start, p->ev_gain[0], p->ev_gain[1], p->ev_chain[0], p->ev_chain[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (p->s2) (void)hipStreamDestroy(p->s2);
     for (void* a : p->allocs) (void)hipFree(a);
     if (p->hstatus) (void)hipHostFree(p->hstatus);
     delete p;

@@ -168,10 +168,9 @@ __device__ __forceinline__ void tri_decode(int t, int& bm, int& bn) {
     bn = t - r * (r + 1) / 2;
 }
 
-// V selects a separately named instantiation: 0 for general products, 1 for the
-// smoother's N x N x N products (so profilers report them on their own).
-template <typename T, int V>
-__global__ __launch_bounds__(NT) void gemm_kernel(GemmGroup G) {
+// Generic path: any alignment or leading dimension, B-operand addends; branchy loads.
+template <typename T>
+__global__ __launch_bounds__(NT) void gemm_generic_kernel(GemmGroup G) {
     __shared__ T As[2][BK * BM];
     __shared__ T Bs[2][BK * BN];
     using AV = typename Acc<T>::V;
@@ -318,7 +317,266 @@ __global__ void gemm_reduce_kernel(GemmProblem P) {
     }
 }
 
+
+// ------------------------------------------------------------------ fast path
+// Branch-free main loop for operands whose leading dimensions are multiples of 8
+// elements with 16-byte aligned bases (all plan-owned buffers). Out-of-range rows
+// and k-steps are read from clamped, in-bounds addresses and replaced by zero with
+// a select, so the loop has no divergent control flow and the accumulators stay in
+// the accumulation registers. Layouts are compile-time (bit 0: A transposed,
+// bit 1: B transposed); a launch can carry problems of two layouts (L0 for the
+// first problem, L1 for the rest).
+
+__device__ __forceinline__ int round8(int v) { return (v + 7) & ~7; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that each XCD
+// works on a contiguous run of tiles (which share operand panels in its L2).
+__device__ __forceinline__ int xcd_remap(int id, int total) {
+    const int xcd = id & 7, local = id >> 3;
+    const int per = total >> 3, rem = total & 7;
+    return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + local;
+}
+
+template <typename T>
+__device__ __forceinline__ void vload8(T (&r)[8], const T* p) {
+    if constexpr (sizeof(T) == 8) {
+        const d2* v = reinterpret_cast<const d2*>(p);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { d2 t = v[q]; r[2 * q] = t.x; r[2 * q + 1] = t.y; }
+    } else {
+        const f4* v = reinterpret_cast<const f4*>(p);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            f4 t = v[q];
+            r[4 * q] = t.x; r[4 * q + 1] = t.y; r[4 * q + 2] = t.z; r[4 * q + 3] = t.w;
+        }
+    }
+}
+
+// One operand of the fast path. "Row-contiguous" (A not transposed / B transposed):
+// the thread owns one row (of the 128) and 8 consecutive k. "K-major" (A transposed /
+// B not transposed): the thread owns one k-row and 8 consecutive rows.
+template <typename T, bool KCONTIG>
+struct Operand {
+    const T* base;      // row base (row-contiguous) or matrix base (k-major)
+    int64_t ld;
+    int rows;           // extent of the 128-dimension (M or N)
+    int K, kcap;        // K extent; last in-bounds 8-segment start along k (row-contiguous)
+    int r0, seg;        // this thread's row (row-contiguous) / k-row (k-major) and segment
+    bool rowok;
+    int segc;           // clamped segment start along the rows (k-major)
+
+    __device__ __forceinline__ void init(const T* M, int64_t ld_, int rows_, int K_, int t0, int tid) {
+        ld = ld_; rows = rows_; K = K_;
+        if constexpr (KCONTIG) {
+            r0 = tid & 127; seg = (tid >> 7) * 8;
+            const int row = t0 + r0;
+            rowok = row < rows;
+            base = M + (int64_t)min(row, rows - 1) * ld;
+            kcap = max(round8(K) - 8, 0);
+        } else {
+            r0 = tid >> 4; seg = (tid & 15) * 8;
+            const int col = t0 + seg;
+            segc = min(col, max(round8(rows) - 8, 0));
+            base = M + segc;
+            rowok = true;
+            kcap = col;        // first row element of this segment (unclamped)
+        }
+    }
+    __device__ __forceinline__ void fetch(T (&r)[8], int k0, int khi) const {
+        T v[8];
+        if constexpr (KCONTIG) {
+            const int gk = k0 + seg;
+            vload8<T>(v, base + min(gk, kcap));
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = (rowok && gk + q < khi) ? v[q] : T(0);
+        } else {
+            const int gk = k0 + r0;
+            vload8<T>(v, base + (int64_t)min(gk, K - 1) * ld);
+            const bool kok = gk < khi;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = (kok && kcap + q < rows) ? v[q] : T(0);
+        }
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void epilogue(const GemmProblem& P, const typename Acc<T>::V (&acc)[4][4], int i0,
+                                         int j0, int split, int tid) {
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int lr = lane & 15, lk = lane >> 4;
+    if (P.ksplit > 1) {
+        T* part = static_cast<T*>(P.partial) + (int64_t)split * P.M * P.N;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + wm + 16 * a + Acc<T>::row(lk, r), j = j0 + wn + 16 * b + lr;
+                    if (i < P.M && j < P.N) part[(int64_t)i * P.N + j] = acc[a][b][r];
+                }
+        return;
+    }
+    const bool lower = P.flags & G_LOWER, mirror = P.flags & G_MIRROR;
+    const bool cin32 = P.flags & G_CIN32, cin2_32 = P.flags & G_CIN2_32;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wm + 16 * a + Acc<T>::row(lk, r), j = j0 + wn + 16 * b + lr;
+                if (i >= P.M || j >= P.N) continue;
+                if (lower && j > i) continue;
+                double v = P.alpha * (double)acc[a][b][r];
+                if (P.Cin) v += P.beta * load_any(P.Cin, cin32, (int64_t)i * P.ldcin + j);
+                if (P.Cin2) v += P.gamma * load_any(P.Cin2, cin2_32, (int64_t)i * P.ldcin2 + j);
+                if (P.C) P.C[(int64_t)i * P.ldc + j] = v;
+                if (P.C32) P.C32[(int64_t)i * P.ldc32 + j] = (float)v;
+                if (P.diag && i == j) P.diag[i] = v;
+                if (mirror && i > j) {
+                    if (P.C) P.C[(int64_t)j * P.ldc + i] = v;
+                    if (P.C32) P.C32[(int64_t)j * P.ldc32 + i] = (float)v;
+                }
+            }
+}
+
+template <typename T, bool TA, bool TB>
+__device__ __forceinline__ void fast_tile(const GemmProblem& P, int bm, int bn, int split, T* As, T* Bs) {
+    using AV = typename Acc<T>::V;
+    const int tid = threadIdx.x;
+    const int i0 = bm * BM, j0 = bn * BN;
+    int klo = 0, khi = P.K;
+    if (P.flags & G_ALOWER) khi = min(khi, i0 + BM);
+    if (P.flags & G_BUPPER) khi = min(khi, j0 + BN);
+    if (P.flags & G_BLOWER) klo = max(klo, j0);
+    if (P.ksplit > 1) {
+        const int span = max(khi - klo, 0);
+        const int chunk = ((span + P.ksplit - 1) / P.ksplit + BK - 1) / BK * BK;
+        klo = klo + split * chunk;
+        khi = min(khi, klo + chunk);
+    }
+    const int nk = khi > klo ? (khi - klo + BK - 1) / BK : 0;
+
+    Operand<T, !TA> oa;
+    Operand<T, TB> ob;
+    oa.init(static_cast<const T*>(P.A), P.lda, P.M, P.K, i0, tid);
+    ob.init(static_cast<const T*>(P.B), P.ldb, P.N, P.K, j0, tid);
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    AV acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = AV{0, 0, 0, 0};
+
+    if (nk > 0) {
+        T ra[8], rb[8];
+        oa.fetch(ra, klo, khi);
+        ob.fetch(rb, klo, khi);
+        stash<T>(As, ra, !TA, tid);
+        stash<T>(Bs, rb, TB, tid);
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            const int k1 = klo + (kt + 1) * BK;
+            // Prefetch the next k-tile (past the end it is fully masked and never stored).
+            oa.fetch(ra, k1, khi);
+            ob.fetch(rb, k1, khi);
+            const T* as = As + cur * (BK * BM);
+            const T* bs = Bs + cur * (BK * BN);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                T fa[4], fb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) fa[a] = as[(kk + lk) * BM + wm + a * 16 + lr];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) fb[b] = bs[(kk + lk) * BN + wn + b * 16 + lr];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = Acc<T>::mfma(fa[a], fb[b], acc[a][b]);
+            }
+            stash<T>(As + (cur ^ 1) * (BK * BM), ra, !TA, tid);
+            stash<T>(Bs + (cur ^ 1) * (BK * BN), rb, TB, tid);
+            __syncthreads();
+        }
+    }
+    epilogue<T>(P, acc, i0, j0, split, tid);
+}
+
+// V selects a separately named instantiation: 1 for the smoother's N x N x N
+// products, so that profilers report them on their own. MASK is the set of operand
+// layouts compiled in (bit L for layout L); each problem of the group picks its own.
+template <typename T, int V, int MASK>
+__global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmGroup G) {
+    __shared__ T As[2 * BK * BM];
+    __shared__ T Bs[2 * BK * BN];
+    // Tiles of equal cost are grouped per XCD; tiles whose K range varies (triangular
+    // operands) keep the round-robin spread so that every XCD gets a fair share.
+    const int bid = G.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    int q = 0;
+#pragma unroll
+    for (int u = 1; u < kMaxGroup; ++u)
+        if (u < G.count && bid >= G.p[u].tile_begin) q = u;
+    const GemmProblem& P = G.p[q];
+    int local = bid - P.tile_begin;
+    const int split = local % P.ksplit;
+    local /= P.ksplit;
+    int bm, bn;
+    if (P.flags & G_LOWER) tri_decode(local, bm, bn);
+    else if (P.flags & G_ALOWER) {            // longest tiles (largest K range) first
+        bm = P.tiles_m - 1 - local / P.tiles_n; bn = local % P.tiles_n;
+    } else if (P.flags & G_BLOWER) {
+        bn = local / P.tiles_m; bm = local % P.tiles_m;
+    } else if (P.flags & G_BUPPER) {
+        bn = P.tiles_n - 1 - local / P.tiles_m; bm = local % P.tiles_m;
+    } else {
+        // Groups of 8 tile rows, column-major inside a group: the 64 workgroups an XCD runs
+        // at once cover about an 8 x 8 block of tiles and share their operand panels in L2.
+        constexpr int GM = 8;
+        const int per_group = GM * P.tiles_n;
+        const int group = local / per_group, first = group * GM;
+        const int gsize = min(P.tiles_m - first, GM);
+        const int in = local - group * per_group;
+        bm = first + in % gsize;
+        bn = in / gsize;
+    }
+    const int lay = (P.flags & G_TA ? 1 : 0) | (P.flags & G_TB ? 2 : 0);
+    if ((MASK & 1) && lay == 0) fast_tile<T, false, false>(P, bm, bn, split, As, Bs);
+    else if ((MASK & 2) && lay == 1) fast_tile<T, true, false>(P, bm, bn, split, As, Bs);
+    else if ((MASK & 4) && lay == 2) fast_tile<T, false, true>(P, bm, bn, split, As, Bs);
+    else if ((MASK & 8) && lay == 3) fast_tile<T, true, true>(P, bm, bn, split, As, Bs);
+}
+
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Fast path requirements for one operand stored with leading dimension ld whose
+// contiguous extent is `contig`: ld a multiple of 8, 16-byte aligned base.
+bool fast_ok(const void* p, int64_t ld, int contig) {
+    return p && aligned16(p) && ld % 8 == 0 && ld >= ((contig + 7) & ~7);
+}
+
+template <typename T, int V>
+hipError_t launch_fast(const GemmGroup& G, int mask, hipStream_t s) {
+    const dim3 grid(G.total_tiles), block(NT);
+#define KF_L(m) hipLaunchKernelGGL((gemm_kernel<T, V, m>), grid, block, 0, s, G)
+    switch (mask) {
+        case 1: KF_L(1); break;
+        case 2: KF_L(2); break;
+        case 4: KF_L(4); break;
+        case 8: KF_L(8); break;
+        case 5: KF_L(5); break;
+        default: KF_L(15); break;
+    }
+#undef KF_L
+    return hipGetLastError();
+}
 
 }  // namespace
 
@@ -327,36 +585,47 @@ hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s) {
     int total = 0;
     const int esz = dt == Dt::F64 ? 8 : 4;
     const int vec_elems = 16 / esz;
+    bool fast = true;
+    int layouts[kMaxGroup] = {};
     for (int u = 0; u < count; ++u) {
         GemmProblem p = probs[u];
         if (p.M <= 0 || p.N <= 0) continue;
         if (p.ksplit < 1) p.ksplit = 1;
         p.tiles_m = (p.M + BM - 1) / BM;
         p.tiles_n = (p.N + BN - 1) / BN;
-        if (p.flags & G_LOWER) {
-            if (p.M != p.N) return hipErrorInvalidValue;
-        }
+        if ((p.flags & G_LOWER) && p.M != p.N) return hipErrorInvalidValue;
+        const bool ta = p.flags & G_TA, tb = p.flags & G_TB;
         bool vec = aligned16(p.A) && aligned16(p.B) && p.lda % vec_elems == 0 && p.ldb % vec_elems == 0;
         if (p.B2) vec = vec && aligned16(p.B2) && p.ldb2 % vec_elems == 0;
         if (p.B3) vec = vec && aligned16(p.B3) && p.ldb3 % vec_elems == 0;
         if (!vec) p.flags |= G_SCALAR;
+        fast = fast && !p.B2 && !p.B3 && p.K > 0 && fast_ok(p.A, p.lda, ta ? p.M : p.K) &&
+               fast_ok(p.B, p.ldb, tb ? p.K : p.N);
         p.tile_begin = total;
         const int tiles = (p.flags & G_LOWER) ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
         total += tiles * p.ksplit;
         if (G.count >= kMaxGroup) return hipErrorInvalidValue;
+        layouts[G.count] = (ta ? 1 : 0) | (tb ? 2 : 0);
         G.p[G.count++] = p;
     }
     if (G.count == 0) return hipSuccess;
     G.total_tiles = total;
-    const bool big = G.p[0].flags & G_NXN;
-    if (dt == Dt::F64) {
-        if (big) hipLaunchKernelGGL((gemm_kernel<double, 1>), dim3(total), dim3(NT), 0, s, G);
-        else hipLaunchKernelGGL((gemm_kernel<double, 0>), dim3(total), dim3(NT), 0, s, G);
-    } else {
-        if (big) hipLaunchKernelGGL((gemm_kernel<float, 1>), dim3(total), dim3(NT), 0, s, G);
-        else hipLaunchKernelGGL((gemm_kernel<float, 0>), dim3(total), dim3(NT), 0, s, G);
+    int mask = 0;
+    G.remap = 1;
+    for (int u = 0; u < G.count; ++u) {
+        mask |= 1 << layouts[u];
+        if (G.p[u].flags & (G_ALOWER | G_BLOWER | G_BUPPER)) G.remap = 0;
     }
-    hipError_t e = hipGetLastError();
+    const bool big = G.p[0].flags & G_NXN;
+    hipError_t e;
+    if (fast) {
+        if (dt == Dt::F64) e = big ? launch_fast<double, 1>(G, mask, s) : launch_fast<double, 0>(G, mask, s);
+        else e = big ? launch_fast<float, 1>(G, mask, s) : launch_fast<float, 0>(G, mask, s);
+    } else {
+        if (dt == Dt::F64) hipLaunchKernelGGL(gemm_generic_kernel<double>, dim3(total), dim3(NT), 0, s, G);
+        else hipLaunchKernelGGL(gemm_generic_kernel<float>, dim3(total), dim3(NT), 0, s, G);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
     for (int u = 0; u < G.count; ++u) {
         const GemmProblem& p = G.p[u];

@@ -42,11 +42,13 @@ struct GemmProblem {
     int tiles_m = 0, tiles_n = 0, tile_begin = 0;
 };
 
-constexpr int kMaxGroup = 4;
+constexpr int kMaxGroup = 8;
+constexpr int kMaxBatch = 4;   // matrices per batched factorisation (two problems each per group)
 struct GemmGroup {
     GemmProblem p[kMaxGroup];
     int count = 0;
     int total_tiles = 0;
+    int remap = 1;     // group equal-cost tiles per XCD (off when K ranges vary per tile)
 };
 
 enum class Dt { F64, F32 };
@@ -67,6 +69,9 @@ enum Which : int { W_S = 1, W_PPRED = 2, W_MNE = 3 };
 // alias W.
 hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, int* status,
                     int which, int step, hipStream_t s);
+// The same for `count` <= kMaxBatch independent matrices of one size, sharing every launch.
+hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z, int64_t ldz, int count,
+                          int* status, int which, const int* steps, hipStream_t s);
 
 // ---------------------------------------------------------------- vector / elementwise kernels
 // e = y - X x  (X: m x N, ld ldx)
@@ -92,6 +97,8 @@ hipError_t copy2d(int rows, int cols, void* dst, bool d32, int64_t ldd,
 hipError_t zero2d(int rows, int cols, double* dst, int64_t ldd, hipStream_t s);
 // scan n values for NaN / Inf; sets *flag = 1 if any
 hipError_t nonfinite_scan(const double* v, int64_t n, int* flag, hipStream_t s);
+// transpose a square matrix in place
+hipError_t transpose_inplace(double* A, int64_t lda, int n, hipStream_t s);
 // store diag of a square double matrix to out
 hipError_t diag_copy(const double* A, int64_t lda, int n, double* out, hipStream_t s);
 

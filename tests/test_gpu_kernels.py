@@ -28,10 +28,19 @@ CASES = [
 ]
 
 
+def _padded(X, dev="cuda"):
+    """Copy X into a buffer whose leading dimension is a multiple of 16 (the fast path's layout)."""
+    r, c = X.shape
+    buf = torch.full((r, (c + 15) // 16 * 16), float("nan"), dtype=X.dtype, device=dev)
+    buf[:, :c] = X.to(dev)
+    return buf[:, :c]
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("M,N,K,flags", CASES)
 @pytest.mark.parametrize("ksplit", [1, 3])
-def test_gemm_layouts(dtype, M, N, K, flags, ksplit):
+@pytest.mark.parametrize("padded", [False, True])
+def test_gemm_layouts(dtype, M, N, K, flags, ksplit, padded):
     g = torch.Generator().manual_seed(M * 7919 + N * 31 + K + flags * 101 + ksplit)
     ta, tb = bool(flags & F.G_TA), bool(flags & F.G_TB)
     A = torch.randn((K, M) if ta else (M, K), generator=g, dtype=torch.float64)
@@ -40,7 +49,10 @@ def test_gemm_layouts(dtype, M, N, K, flags, ksplit):
     alpha, beta = -0.75, 1.25
     Ad, Bd = A.to(dtype), B.to(dtype)
     ref = alpha * (_op(Ad.double(), ta) @ _op(Bd.double(), tb)) + beta * Cin
-    C = F.kfd_gemm(Ad.cuda(), Bd.cuda(), M, N, K, flags, alpha, beta, Cin.cuda(), ksplit=ksplit).cpu()
+    if padded:   # NaN padding: any read past the logical extent would poison the result
+        C = F.kfd_gemm(_padded(Ad), _padded(Bd), M, N, K, flags, alpha, beta, Cin.cuda(), ksplit=ksplit).cpu()
+    else:
+        C = F.kfd_gemm(Ad.cuda(), Bd.cuda(), M, N, K, flags, alpha, beta, Cin.cuda(), ksplit=ksplit).cpu()
     tol = (1e-13 if dtype == torch.float64 else 2e-6) * K ** 0.5 * 4 + (1e-14 if dtype == torch.float64 else 1e-6)
     if flags & F.G_LOWER:
         low = torch.tril(torch.ones(M, N, dtype=torch.bool))
@@ -55,24 +67,26 @@ def test_gemm_layouts(dtype, M, N, K, flags, ksplit):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("n,k", [(200, 200), (300, 130), (129, 257)])
-def test_gemm_triangular_operands(dtype, n, k):
+@pytest.mark.parametrize("padded", [False, True])
+def test_gemm_triangular_operands(dtype, n, k, padded):
     g = torch.Generator().manual_seed(n + k)
+    dev = _padded if padded else (lambda X: X.cuda())
     # A lower triangular (n x n) times B (n x k)
     A = torch.tril(torch.randn(n, n, generator=g, dtype=torch.float64)).to(dtype)
     B = torch.randn(n, k, generator=g, dtype=torch.float64).to(dtype)
-    C = F.kfd_gemm(A.cuda(), B.cuda(), n, k, n, F.G_ALOWER).cpu()
+    C = F.kfd_gemm(dev(A), dev(B), n, k, n, F.G_ALOWER).cpu()
     ref = A.double() @ B.double()
     tol = 1e-12 if dtype == torch.float64 else 2e-5
     assert (C - ref).abs().max() <= tol * ref.abs().max()
     # G^T L with L lower (B lower: B(k,j) = 0 for k < j)
     G = torch.randn(n, k, generator=g, dtype=torch.float64).to(dtype)
     L = torch.tril(torch.randn(n, n, generator=g, dtype=torch.float64)).to(dtype)
-    C = F.kfd_gemm(G.cuda(), L.cuda(), k, n, n, F.G_TA | F.G_BLOWER).cpu()
+    C = F.kfd_gemm(dev(G), dev(L), k, n, n, F.G_TA | F.G_BLOWER).cpu()
     ref = G.double().T @ L.double()
     assert (C - ref).abs().max() <= tol * ref.abs().max()
     # X L^T with L lower: B(k,j) = L[j][k], upper in (k,j)
     X = torch.randn(k, n, generator=g, dtype=torch.float64).to(dtype)
-    C = F.kfd_gemm(X.cuda(), L.cuda(), k, n, n, F.G_TB | F.G_BUPPER).cpu()
+    C = F.kfd_gemm(dev(X), dev(L), k, n, n, F.G_TB | F.G_BUPPER).cpu()
     ref = X.double() @ L.double().T
     assert (C - ref).abs().max() <= tol * ref.abs().max()
 
