@@ -254,7 +254,7 @@ kf_status sync_and_check(kf_plan* p, const char* phase) {
 
 // Launch a group of the smoother's N x N x N products (named instantiation), timed when profiling.
 kf_status big_group(kf_plan* p, Dt dt, GemmProblem* g, int count, double flops, hipStream_t st) {
-    for (int u = 0; u < count; ++u) g[u].flags |= G_NXN;
+    for (int u = 0; u < count; ++u) g[u].flags |= mixed(p) ? G_NXN_MIXED : G_NXN;
     if (p->prof) {
         while (p->ev.size() < p->ev_used + 2) {
             hipEvent_t e;

@@ -511,7 +511,8 @@ __device__ __forceinline__ void fast_tile(const GemmProblem& P, int bm, int bn, 
 }
 
 // V selects a separately named instantiation: 1 for the smoother's N x N x N
-// products, so that profilers report them on their own. MASK is the set of operand
+// products of the float64 path, 2 for those of the mixed path, so that profilers
+// report them on their own. MASK is the set of operand
 // layouts compiled in (bit L for layout L); each problem of the group picks its own.
 template <typename T, int V, int MASK>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmGroup G) {
@@ -616,11 +617,14 @@ hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s) {
         mask |= 1 << layouts[u];
         if (G.p[u].flags & (G_ALOWER | G_BLOWER | G_BUPPER)) G.remap = 0;
     }
-    const bool big = G.p[0].flags & G_NXN;
+    const int variant = (G.p[0].flags & G_NXN) ? 1 : (G.p[0].flags & G_NXN_MIXED) ? 2 : 0;
     hipError_t e;
     if (fast) {
-        if (dt == Dt::F64) e = big ? launch_fast<double, 1>(G, mask, s) : launch_fast<double, 0>(G, mask, s);
-        else e = big ? launch_fast<float, 1>(G, mask, s) : launch_fast<float, 0>(G, mask, s);
+        if (dt == Dt::F64)
+            e = variant == 1 ? launch_fast<double, 1>(G, mask, s)
+              : variant == 2 ? launch_fast<double, 2>(G, mask, s) : launch_fast<double, 0>(G, mask, s);
+        else
+            e = variant == 2 ? launch_fast<float, 2>(G, mask, s) : launch_fast<float, 0>(G, mask, s);
     } else {
         if (dt == Dt::F64) hipLaunchKernelGGL(gemm_generic_kernel<double>, dim3(total), dim3(NT), 0, s, G);
         else hipLaunchKernelGGL(gemm_generic_kernel<float>, dim3(total), dim3(NT), 0, s, G);

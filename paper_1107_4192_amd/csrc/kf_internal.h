@@ -21,7 +21,8 @@ enum GemmFlags : int {
     G_BUPPER = 64,     // B(k,j) = 0 for k > j
     G_CIN32 = 128,     // Cin is float (else double)
     G_CIN2_32 = 256,   // Cin2 is float (else double)
-    G_NXN = 512,       // launch the separately named instantiation for the smoother's N x N x N products
+    G_NXN = 512,       // separately named instantiation: smoother N x N x N products, float64 path
+    G_NXN_MIXED = 1024,// separately named instantiation: the same products in the mixed-precision path
 };
 
 struct GemmProblem {
