@@ -6,7 +6,7 @@ model (eqn1, eqn3 with F = I), so that the HIP path and the CPU oracle consume
 the very same arrays.
 
 The paper's own inputs (a subject MRI, a BEM lead field, Vectorview
-recordings, empty-room noise; Section 4.1 and 4.2) are not available, so every
+recordings, empty-room noise; Sections 4.1 and 5) are not available, so every
 workload here is synthetic with the paper's shapes: about 5,120 normal-oriented
 cortical sources, 306 sensors (102 sites x 3 channels), 600 Hz sampling and
 about 125 active sources in three regions (Section 4.1).
