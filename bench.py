@@ -12,9 +12,12 @@ Besides the contract's JSON fields the line carries:
   cpu_baseline  the FP64 oracle timed on this host on a bounded sample (the first 10 steps
                 of the same workload at full N: filter 10 steps + smoother 9 steps);
   mixed         the same workload in mixed precision (FP32 MFMA bulk, FP64 factorisations,
-                FP32 store): its rate, speedup over FP64 and its error against the FP64 path.
+                FP32 store): its rate, speedup over FP64 and its error against the FP64 path;
+  serving       p50/p99 job latency and throughput of the continuous-batching server on a
+                Poisson stream of jobs of mixed N, m, T, against the same jobs run one at a
+                time in FP64.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--T 200] [--no-cpu] [--no-mixed]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--T 200] [--no-cpu] [--no-mixed] [--no-serving]
 """
 from __future__ import annotations
 
@@ -129,6 +132,59 @@ def run_gpu(p, precision, steps, warmup, store_fp32=False, profile=False):
     return out
 
 
+def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(102, 204, 306),
+                T_range=(20, 60), max_active=4):
+    """Serving form: Poisson arrivals of filter+smoother jobs of mixed shapes, mixed precision
+    with float32 stores, continuously batched; against the same jobs one at a time in FP64."""
+    import numpy as np
+    import torch
+    from paper_1107_4192_amd import kfmeg, synth
+
+    plan = synth.serving_jobs(seed=seed, n_jobs=n_jobs, rate_per_s=rate, N_choices=N_choices,
+                              m_choices=m_choices, T_range=T_range)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    jobs = []
+    for j in plan:
+        p = synth.custom(j["seed"], j["N"], j["m"], j["T"])
+        jobs.append((j, tuple(dev(a) for a in (p.X, p.Q, p.R, p.x0, p.P0, p.Y))))
+    log(f"serving: {n_jobs} jobs generated in {time.perf_counter() - t0:.1f} s")
+    # continuous batching, mixed precision + float32 store
+    srv = kfmeg.Server(max_active=max_active, precision=kfmeg.KF_MIXED, store_fp32=True)
+    ids = []
+    start = time.perf_counter()
+    for j, arrs in jobs:
+        delay = start + j["arrival_s"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(*arrs))
+    for i in ids:
+        srv.wait(i)
+    st = srv.stats()
+    infos = [srv.info(i) for i in ids]
+    srv.close()
+    log(f"serving: {st['completed']} jobs, p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms")
+    # baseline: the same jobs one at a time in plain FP64
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j, arrs in jobs:
+        ks = kfmeg.KalmanSmoother(*arrs[:5], T_max=j["T"])
+        ks.run(arrs[5])
+        ks.close()
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    steps = sum(j["T"] for j, _ in jobs)
+    log(f"serving: sequential FP64 {seq:.1f} s")
+    return {"workload": f"{n_jobs} jobs, Poisson arrivals {rate}/s, N in {list(N_choices)}, "
+                        f"m in {list(m_choices)}, T in {list(T_range)}; mixed precision, float32 store",
+            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "jobs_per_s": st["jobs_per_s"],
+            "steps_per_s": st["steps_per_s"], "max_concurrent": st["max_concurrent"],
+            "checkpointed": st["checkpointed"], "peak_gib": st["peak_bytes"] / 2 ** 30,
+            "sequential_fp64_steps_per_s": steps / seq,
+            "throughput_speedup_vs_sequential_fp64": st["steps_per_s"] / (steps / seq),
+            "mean_queue_ms": float(np.mean([i["queued_ms"] for i in infos]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +196,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 256 MiB copy first (HBM counter scale)")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the multi-GPU sharding "
@@ -198,6 +255,8 @@ def main():
                          "eps_x_smooth_vs_fp64_path": ex, "eps_diagP_smooth_vs_fp64_path": ed,
                          "store": "fp32", "filter_s_per_pass": rmx["t_filter"],
                          "smoother_s_per_pass": rmx["t_smooth"]}
+    if not args.no_serving:
+        line["serving"] = run_serving()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)

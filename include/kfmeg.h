@@ -141,6 +141,51 @@ kf_status kf_get_profile(const kf_plan* plan, double* kernel_ms, double* kernel_
  */
 size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt);
 
+/*
+ * Serving: continuous batching of filter + smoother jobs (kf_filter then
+ * kf_smooth) of different N, m and T on one GPU.
+ *
+ * kfs_create reserves one device arena of hbm_budget_bytes (0 = free HBM less
+ * 4 GiB) and starts max_active worker slots, each with its own stream. Jobs are
+ * taken in arrival order; a job starts as soon as a slot is free and its plan
+ * (workspaces, covariance store, filtered means; kf_plan_bytes) fits in the
+ * arena next to the running jobs. If the full store of P_{t|t} does not fit, the
+ * job starts with the smallest checkpoint stride that fits instead of waiting.
+ * Running jobs' kernels overlap on the device; a job's results do not depend on
+ * the other jobs. `opt` sets the precision and store type of every job.
+ *
+ * kfs_submit enqueues a job and returns at once. All array arguments are device
+ * pointers as in kf_create / kf_smooth and must stay valid until kfs_wait for
+ * that job returns. x_smooth (T x N) and Pdiag_smooth (T x N, or NULL) receive
+ * x_{t|T} and diag P_{t|T}.
+ * kfs_wait blocks until the job is done and returns its status (KF_ENOTPD,
+ * KF_ENOMEM if it can never fit the budget, ...); latency_ms = completion minus
+ * submission.
+ * kfs_get_stats: latency percentiles over completed jobs, throughput over the
+ * span from the first submission to the last completion, peak arena use (never
+ * above the budget) and the most jobs that ran at once.
+ * kfs_destroy waits for queued and running jobs, then frees everything.
+ */
+typedef struct kfs_server kfs_server;
+typedef struct {
+    double p50_ms, p99_ms, mean_ms, max_ms;
+    double jobs_per_s, steps_per_s;
+    int64_t submitted, completed, failed, checkpointed;
+    size_t peak_bytes, budget_bytes;
+    int max_concurrent;
+} kfs_stats;
+
+kf_status kfs_create(kfs_server** out, size_t hbm_budget_bytes, int max_active, const kf_options* opt);
+kf_status kfs_submit(kfs_server* srv, int64_t N, int64_t m, int64_t T, const double* X, const double* Q,
+                     const double* R, const double* x0, const double* P0, const double* Y,
+                     double* x_smooth, double* Pdiag_smooth, int64_t* job_id);
+kf_status kfs_wait(kfs_server* srv, int64_t job_id, double* latency_ms);
+kf_status kfs_job_info(kfs_server* srv, int64_t job_id, int* done, int* checkpoint_stride,
+                       double* queued_ms, double* run_ms);
+kf_status kfs_get_stats(kfs_server* srv, kfs_stats* out);
+const char* kfs_last_error(kfs_server* srv);
+void kfs_destroy(kfs_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

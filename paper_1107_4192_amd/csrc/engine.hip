@@ -23,6 +23,7 @@
 // Cholesky of S and of P_{t+1|t}, the gain A_t and every epilogue in FP64, and
 // may store P_{t|t} in FP32.
 #include "kf_internal.h"
+#include "arena.h"
 #include "../../include/kfmeg.h"
 
 #include <cmath>
@@ -39,6 +40,7 @@ struct kf_plan {
     hipStream_t stream = nullptr;
     int64_t ldN = 0, ldm = 0;
     std::vector<void*> allocs;
+    DeviceArena* arena = nullptr;           // serving: buffers come from the server's arena
 
     // model
     double *X = nullptr, *Q = nullptr, *R = nullptr, *x0 = nullptr, *P0 = nullptr;
@@ -87,7 +89,7 @@ struct kf_plan {
 
 namespace {
 
-std::string g_err;
+thread_local std::string g_err;
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -106,19 +108,30 @@ struct Fail {
 
 bool mixed(const kf_plan* p) { return p->opt.precision == KF_MIXED; }
 
-template <typename T>
-kf_status alloc(kf_plan* p, T** out, size_t elems) {
+kf_status alloc_bytes(kf_plan* p, void** out, size_t bytes) {
     void* ptr = nullptr;
-    if (elems == 0) elems = 1;
-    hipError_t e = hipMalloc(&ptr, elems * sizeof(T));
-    if (e != hipSuccess) {
+    if (bytes == 0) bytes = 1;
+    if (p->arena) {
+        ptr = p->arena->alloc(bytes);
+    } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        p->err = "device allocation of " + std::to_string(elems * sizeof(T)) + " bytes failed";
+        ptr = nullptr;
+    }
+    if (!ptr) {
+        p->err = "device allocation of " + std::to_string(bytes) + " bytes failed";
         return KF_ENOMEM;
     }
     p->allocs.push_back(ptr);
-    *out = static_cast<T*>(ptr);
+    *out = ptr;
     return KF_OK;
+}
+
+template <typename T>
+kf_status alloc(kf_plan* p, T** out, size_t elems) {
+    void* ptr = nullptr;
+    kf_status st = alloc_bytes(p, &ptr, (elems ? elems : 1) * sizeof(T));
+    if (st == KF_OK) *out = static_cast<T*>(ptr);
+    return st;
 }
 
 #define TRY(expr)                           \
@@ -313,8 +326,14 @@ size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt) {
            store_bytes(N, ldN, T, o.store_fp32, stride);
 }
 
-kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const double* X, const double* Q,
-                    const double* R, const double* x0, const double* P0, const kf_options* opt, void* stream) {
+}  // extern "C"
+
+namespace kfmeg {
+
+// kf_create with an optional arena for every device buffer of the plan (serving).
+kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const double* X, const double* Q,
+                      const double* R, const double* x0, const double* P0, const kf_options* opt, void* stream,
+                      DeviceArena* arena) {
     if (!out) return KF_EINVAL;
     *out = nullptr;
     if (N <= 0 || m <= 0 || T_max <= 0 || N > (1 << 20) || m > (1 << 16)) {
@@ -326,6 +345,7 @@ kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const do
         return KF_EINVAL;
     }
     kf_plan* p = new kf_plan();
+    p->arena = arena;
     p->N = N; p->m = m; p->Tmax = T_max;
     kf_default_options(&p->opt);
     if (opt) p->opt = *opt;
@@ -341,6 +361,7 @@ kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const do
 
     // Store layout: all T_max slots, or every k-th slot when over budget.
     size_t budget = p->opt.hbm_budget_bytes;
+    if (budget == 0 && arena) budget = arena->largest_free();
     if (budget == 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) budget = fr > ((size_t)1 << 30) ? fr - ((size_t)1 << 30) : 0;
@@ -400,20 +421,16 @@ kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const do
     {
         void* sp = nullptr;
         const size_t bytes = (size_t)p->nslots * NN * (p->store32 ? 4 : 8);
-        if (hipMalloc(&sp, bytes) != hipSuccess) {
-            (void)hipGetLastError();
+        if ((st = alloc_bytes(p, &sp, bytes)) != KF_OK) {
             p->err = "device allocation of the covariance store (" + std::to_string(bytes) + " bytes) failed";
-            return fail(KF_ENOMEM);
+            return fail(st);
         }
-        p->allocs.push_back(sp);
         p->store = sp;
         if (stride > 1) {
-            if (hipMalloc(&sp, (size_t)stride * NN * (p->store32 ? 4 : 8)) != hipSuccess) {
-                (void)hipGetLastError();
+            if ((st = alloc_bytes(p, &sp, (size_t)stride * NN * (p->store32 ? 4 : 8))) != KF_OK) {
                 p->err = "device allocation of the recompute segment failed";
-                return fail(KF_ENOMEM);
+                return fail(st);
             }
-            p->allocs.push_back(sp);
             p->seg = sp;
         }
     }
@@ -457,6 +474,27 @@ kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const do
     }
     *out = p;
     return KF_OK;
+}
+
+// Device bytes of a plan with gain-batch width gb (kf_plan_bytes uses the widest).
+size_t plan_bytes_ex(int64_t N, int64_t m, int64_t T, const kf_options* opt, int gb) {
+    kf_options o;
+    kf_default_options(&o);
+    if (opt) o = *opt;
+    if (N <= 0 || m <= 0 || T <= 0) return 0;
+    const int64_t ldN = round_up(N, 16);
+    const int stride = o.checkpoint_stride > 0 ? o.checkpoint_stride : 1;
+    return workspace_bytes(N, m, o.precision == KF_MIXED, o.store_fp32, stride, gb) +
+           store_bytes(N, ldN, T, o.store_fp32, stride);
+}
+
+}  // namespace kfmeg
+
+extern "C" {
+
+kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const double* X, const double* Q,
+                    const double* R, const double* x0, const double* P0, const kf_options* opt, void* stream) {
+    return create_plan(out, N, m, T_max, X, Q, R, x0, P0, opt, stream, nullptr);
 }
 
 static kf_status filter_impl(kf_plan* p, int64_t T, const double* Y, double* x_filt, double* Pdiag) {
@@ -786,7 +824,10 @@ void kf_destroy(kf_plan* p) {
     for (hipEvent_t e : {p->ev_start, p->ev_gain[0], p->ev_gain[1], p->ev_chain[0], p->ev_chain[1]})
         if (e) (void)hipEventDestroy(e);
     if (p->s2) (void)hipStreamDestroy(p->s2);
-    for (void* a : p->allocs) (void)hipFree(a);
+    for (void* a : p->allocs) {
+        if (p->arena) p->arena->release(a);
+        else (void)hipFree(a);
+    }
     if (p->hstatus) (void)hipHostFree(p->hstatus);
     delete p;
 }

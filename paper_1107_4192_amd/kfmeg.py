@@ -21,13 +21,26 @@ _STATUS = {0: "KF_OK", 1: "KF_EINVAL", 2: "KF_ENOTPD", 3: "KF_ENOMEM", 4: "KF_EH
 
 # Every function the header declares; a CPU test checks the library exports them all.
 EXPORTS = ("kf_default_options", "kf_create", "kf_filter", "kf_smooth", "kf_get_filtered_cov",
-           "mne_solve", "kf_destroy", "kf_last_error", "kf_plan_bytes", "kfd_gemm", "kfd_chol_inv", "kf_set_profiling", "kf_get_profile")
+           "mne_solve", "kf_destroy", "kf_last_error", "kf_plan_bytes", "kfd_gemm", "kfd_chol_inv", "kf_set_profiling", "kf_get_profile",
+           "kfs_create", "kfs_submit", "kfs_wait", "kfs_job_info", "kfs_get_stats", "kfs_last_error",
+           "kfs_destroy")
 
 
 class KFError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class kfs_stats(ctypes.Structure):
+    _fields_ = [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("jobs_per_s", ctypes.c_double), ("steps_per_s", ctypes.c_double),
+                ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("checkpointed", ctypes.c_int64), ("peak_bytes", ctypes.c_size_t),
+                ("budget_bytes", ctypes.c_size_t), ("max_concurrent", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class kf_options(ctypes.Structure):
@@ -71,6 +84,21 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64)]
     lib.kf_get_profile.restype = ctypes.c_int
+    lib.kfs_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(kf_options)]
+    lib.kfs_create.restype = ctypes.c_int
+    lib.kfs_submit.argtypes = [vp, i64, i64, i64, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(i64)]
+    lib.kfs_submit.restype = ctypes.c_int
+    lib.kfs_wait.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
+    lib.kfs_wait.restype = ctypes.c_int
+    lib.kfs_job_info.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.kfs_job_info.restype = ctypes.c_int
+    lib.kfs_get_stats.argtypes = [vp, ctypes.POINTER(kfs_stats)]
+    lib.kfs_get_stats.restype = ctypes.c_int
+    lib.kfs_last_error.argtypes = [vp]
+    lib.kfs_last_error.restype = ctypes.c_char_p
+    lib.kfs_destroy.argtypes = [vp]
+    lib.kfs_destroy.restype = None
     lib.kfd_gemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, i64, dp,
                              i64, ctypes.c_double, ctypes.c_double, dp, i64, dp, i64, ctypes.c_int, vp]
     lib.kfd_gemm.restype = ctypes.c_int
@@ -187,6 +215,72 @@ def mne_solve(X, C, R, Y, J=None, stream=None):
                        _dev(Y, "Y", (T, m)), _dev(J, "J", (T, N)), _stream_ptr(stream))
     _check(lib, st, None)
     return J
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching server (kfs_* in kfmeg.h). submit() returns a job id; the
+    tensors handed to a job must stay alive until wait() for it returns."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_active: int = 4, precision: int = KF_FP64,
+                 store_fp32: bool = False):
+        lib = load_library()
+        _need_gpu()
+        self._lib = lib
+        self._keep = {}
+        h = ctypes.c_void_p()
+        opt = options(precision, store_fp32)
+        st = lib.kfs_create(ctypes.byref(h), int(hbm_budget_bytes), int(max_active), ctypes.byref(opt))
+        if st != KF_OK:
+            raise KFError(st, "kfs_create failed")
+        self.h = h.value
+
+    def submit(self, X, Q, R, x0, P0, Y, want_diag: bool = True):
+        m, N = X.shape
+        T = Y.shape[0]
+        xs = torch.empty((T, N), dtype=torch.float64, device=X.device)
+        ds = torch.empty((T, N), dtype=torch.float64, device=X.device) if want_diag else None
+        jid = ctypes.c_int64()
+        st = self._lib.kfs_submit(self.h, N, m, T, _dev(X, "X", (m, N)), _dev(Q, "Q", (N, N)),
+                                  _dev(R, "R", (m, m)), _dev(x0, "x0", (N,)), _dev(P0, "P0", (N, N)),
+                                  _dev(Y, "Y", (T, m)), xs.data_ptr(), ds.data_ptr() if ds is not None else None,
+                                  ctypes.byref(jid))
+        if st != KF_OK:
+            raise KFError(st, "kfs_submit failed")
+        self._keep[jid.value] = (X, Q, R, x0, P0, Y, xs, ds)
+        return jid.value
+
+    def wait(self, job_id: int):
+        """Block until the job is done: returns (x_smooth, Pdiag_smooth, latency_ms)."""
+        lat = ctypes.c_double()
+        st = self._lib.kfs_wait(self.h, job_id, ctypes.byref(lat))
+        bufs = self._keep.pop(job_id)
+        if st != KF_OK:
+            msg = self._lib.kfs_last_error(self.h)
+            raise KFError(st, msg.decode() if msg else "")
+        return bufs[6], bufs[7], lat.value
+
+    def info(self, job_id: int) -> dict:
+        d, s, q, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        _check(self._lib, self._lib.kfs_job_info(self.h, job_id, ctypes.byref(d), ctypes.byref(s), ctypes.byref(q),
+                                                 ctypes.byref(r)))
+        return {"done": bool(d.value), "checkpoint_stride": s.value, "queued_ms": q.value, "run_ms": r.value}
+
+    def stats(self) -> dict:
+        out = kfs_stats()
+        _check(self._lib, self._lib.kfs_get_stats(self.h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.kfs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- kernel-level hooks (tests)
