@@ -185,6 +185,47 @@ def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(
             "mean_queue_ms": float(np.mean([i["queued_ms"] for i in infos]))}
 
 
+def run_free(T=100, budget_gib=64.0):
+    """Free-orientation workload (N = 15372 = 5124 sites x 3, m = 306): mixed precision, float32
+    store; once with the whole store in HBM and once under an HBM budget that forces
+    checkpoint-and-recompute. Results must agree bit for bit."""
+    import numpy as np
+    import torch
+    from paper_1107_4192_amd import kfmeg, synth
+
+    t0 = time.perf_counter()
+    p = synth.free(T=T)
+    log(f"free-orientation workload N={p.N} m={p.m} T={p.T} generated in {time.perf_counter() - t0:.1f} s")
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    arrs = [dev(a) for a in (p.X, p.Q, p.R, p.x0, p.P0, p.Y)]
+    out = {"workload": f"free orientation: N={p.N} (5124 sites x 3), m={p.m}, T={p.T}, mixed precision, "
+                       "float32 store"}
+    ref = None
+    for label, budget in (("full_store", 0), ("checkpointed", int(budget_gib * 2 ** 30))):
+        ks = kfmeg.KalmanSmoother(*arrs[:5], T_max=p.T, precision=kfmeg.KF_MIXED, store_fp32=True,
+                                  hbm_budget_bytes=budget)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        res = ks.filter(arrs[5])
+        b = time.perf_counter()
+        ks.smooth(res)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        ks.close()
+        log(f"free ({label}): filter {b - a:.1f} s, smoother {c - b:.1f} s")
+        out[label] = {"steps_per_s": p.T / (c - a), "filter_s": b - a, "smoother_s": c - b,
+                      "hbm_budget_gib": budget / 2 ** 30 if budget else None,
+                      "plan_gib": kfmeg.kf_plan_bytes(p.N, p.m, p.T, kfmeg.options(kfmeg.KF_MIXED, True)) / 2 ** 30}
+        if ref is None:
+            ref = (res.x_smooth.clone(), res.Pdiag_smooth.clone())
+        else:
+            out["checkpointed_equals_full_store"] = bool(torch.equal(ref[0], res.x_smooth) and
+                                                         torch.equal(ref[1], res.Pdiag_smooth))
+        del res
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +238,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 256 MiB copy first (HBM counter scale)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--workload", choices=("paper", "free"), default="paper",
+                    help="free: run the free-orientation N=15372 workload only (full store and checkpointed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the multi-GPU sharding "
@@ -210,6 +253,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
 
+    if args.workload == "free":
+        print(json.dumps({"free_orientation": run_free(T=min(args.T, 100))}), flush=True)
+        return
     if args.calib_copy:
         calibration_copy()
     t0 = time.perf_counter()

@@ -35,7 +35,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-__all__ = ["kf_update", "kf_filter", "smoother_gain", "rts_smooth", "mne_solve"]
+__all__ = ["kf_update", "kf_filter", "smoother_gain", "rts_smooth", "rts_step_columns", "mne_solve"]
 
 
 def _chol(A: np.ndarray):
@@ -113,6 +113,25 @@ def rts_smooth(xf: np.ndarray, Pf: np.ndarray, Q: np.ndarray):
         Ps[t] = (Pst + Pst.T) / 2.0
         dPs[t] = np.diag(Ps[t])
     return xs, Ps, dPs
+
+
+def rts_step_columns(x_filt: np.ndarray, P_filt: np.ndarray, x_next_smooth: np.ndarray,
+                     P_next_smooth: np.ndarray, Q: np.ndarray, cols):
+    """One smoother step (eqn11-eqn13, RTS reading) at selected columns only.
+
+    Returns x_{t|T} in full and the columns `cols` of P_{t|T}, from one Cholesky factorisation
+    of P_{t+1|t} = P_{t|t} + Q and solves with single right-hand sides, so that large N is
+    affordable: A_t v = P_{t|t} (P_{t+1|t}^{-1} v) and A_t^T e_i = P_{t+1|t}^{-1} P_{t|t} e_i.
+    """
+    P_next_pred = P_filt + Q                                     # eqn7
+    c = _chol(P_next_pred)
+    d = x_next_smooth - x_filt                                   # x_{t+1|T} - x_{t+1|t}, F = I
+    xs = x_filt + P_filt @ sla.cho_solve(c, d)                   # eqn12 (RTS reading)
+    D = P_next_smooth - P_next_pred
+    cols = list(cols)
+    At_e = sla.cho_solve(c, P_filt[:, cols])                     # A_t^T e_i, one column per i
+    Pcols = P_filt[:, cols] + P_filt @ sla.cho_solve(c, D @ At_e)   # eqn13 (RTS reading)
+    return xs, Pcols
 
 
 def mne_solve(X, C, R, Y) -> np.ndarray:

@@ -142,8 +142,13 @@ kf_status alloc(kf_plan* p, T** out, size_t elems) {
 
 size_t slot_elems(const kf_plan* p) { return (size_t)p->N * p->ldN; }
 
+// Kept slots are float64 unless the whole store is float32 (stride 1): checkpoints stay
+// float64 so that recomputed covariances match the full store bit for bit (a float32
+// store is emulated by rounding wherever the smoother reads a covariance).
+bool slot64(const kf_plan* p) { return !p->store32 || p->stride > 1; }
+
 void* slot_ptr(const kf_plan* p, int64_t idx) {
-    const size_t esz = p->store32 ? 4 : 8;
+    const size_t esz = slot64(p) ? 8 : 4;
     return static_cast<char*>(p->store) + (size_t)idx * slot_elems(p) * esz;
 }
 
@@ -157,7 +162,7 @@ int64_t slot_of(const kf_plan* p, int64_t t, int64_t T) {
 int64_t slots_needed(int64_t T, int stride) { return stride == 1 ? T : T / stride + 1; }
 
 size_t store_bytes(int64_t N, int64_t ldN, int64_t T, bool s32, int stride) {
-    return (size_t)slots_needed(T, stride) * (size_t)N * ldN * (s32 ? 4 : 8);
+    return (size_t)slots_needed(T, stride) * (size_t)N * ldN * (s32 && stride == 1 ? 4 : 8);
 }
 
 size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int gb) {
@@ -420,7 +425,7 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     if (p->store32 || stride > 1) { ALLOC(p->Pw[0], NN); ALLOC(p->Pw[1], NN); }
     {
         void* sp = nullptr;
-        const size_t bytes = (size_t)p->nslots * NN * (p->store32 ? 4 : 8);
+        const size_t bytes = (size_t)p->nslots * NN * (slot64(p) ? 8 : 4);
         if ((st = alloc_bytes(p, &sp, bytes)) != KF_OK) {
             p->err = "device allocation of the covariance store (" + std::to_string(bytes) + " bytes) failed";
             return fail(st);
@@ -514,10 +519,10 @@ static kf_status filter_impl(kf_plan* p, int64_t T, const double* Y, double* x_f
     for (int64_t t = 0; t < T; ++t) {
         double* out64 = direct ? static_cast<double*>(slot_ptr(p, t)) : p->Pw[t & 1];
         float* out32 = nullptr;
-        if (p->store32 && kept(p, t, T)) out32 = static_cast<float*>(slot_ptr(p, slot_of(p, t, T)));
+        if (!slot64(p) && kept(p, t, T)) out32 = static_cast<float*>(slot_ptr(p, slot_of(p, t, T)));
         TRY(filter_cov_step(p, t, prev64, out64, out32, Pdiag ? Pdiag + t * N : nullptr, Y + t * m,
                             x_filt + t * N));
-        if (!direct && !p->store32 && kept(p, t, T)) {
+        if (!direct && slot64(p) && kept(p, t, T)) {
             HIPCK(hipMemcpyAsync(slot_ptr(p, slot_of(p, t, T)), out64, slot_elems(p) * 8, hipMemcpyDeviceToDevice,
                                  s));
         }
@@ -557,8 +562,8 @@ kf_status recompute_segment(kf_plan* p, int64_t t0, int64_t t1, int64_t T) {
     if (t0 == 0) {
         prev64 = p->P0;
     } else {
-        const void* src = slot_ptr(p, slot_of(p, t0 - 1, T));
-        HIPCK(copy2d((int)p->N, (int)p->N, p->Pw[0], false, p->ldN, src, s32, p->ldN, s));
+        const void* src = slot_ptr(p, slot_of(p, t0 - 1, T));   // float64 checkpoint
+        HIPCK(copy2d((int)p->N, (int)p->N, p->Pw[0], false, p->ldN, src, false, p->ldN, s));
         prev64 = p->Pw[0];
     }
     for (int64_t t = t0; t <= t1; ++t) {
@@ -576,15 +581,16 @@ kf_status recompute_segment(kf_plan* p, int64_t t0, int64_t t1, int64_t T) {
 // t = ts[b], formed as G = Li P_t, A_t = G^T Li with L Li = chol(P_t + Q), into gain set
 // `set`. The steps are independent given the stored P_{t|t}, so every launch covers the
 // whole batch.
-kf_status gain_batch(kf_plan* p, int set, int count, const int64_t* ts, const void* const* Pt, hipStream_t s) {
+kf_status gain_batch(kf_plan* p, int set, int count, const int64_t* ts, const void* const* Pt, const bool* is32,
+                     hipStream_t s) {
     const int N = (int)p->N;
     const int64_t ld = p->ldN;
     const double* P64[kMaxBatch];
     int steps[kMaxBatch];
     for (int b = 0; b < count; ++b) {
         P64[b] = static_cast<const double*>(Pt[b]);
-        if (p->store32) {
-            HIPCK(copy2d(N, N, p->Pt64[set][b], false, ld, Pt[b], true, ld, s));
+        if (p->store32) {        // the float32 store's value, whether read from it or from a checkpoint
+            HIPCK(copy2d_r32(N, N, p->Pt64[set][b], ld, Pt[b], is32[b], ld, s));
             P64[b] = p->Pt64[set][b];
         }
         // W = P_t + Q  (= P_{t+1|t}, eqn7)
@@ -666,7 +672,8 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
     HIPCK(hipMemsetAsync(p->dstatus, 0, 4 * sizeof(int), s));
     // t = T-1: smoother = filter
     const void* PT = slot_ptr(p, slot_of(p, T - 1, T));
-    HIPCK(copy2d((int)N, (int)N, p->Ps[(T - 1) & 1], false, ld, PT, s32, ld, s));
+    if (s32) HIPCK(copy2d_r32((int)N, (int)N, p->Ps[(T - 1) & 1], ld, PT, !slot64(p), ld, s));
+    else HIPCK(copy2d((int)N, (int)N, p->Ps[(T - 1) & 1], false, ld, PT, false, ld, s));
     HIPCK(hipMemcpyAsync(xs + (T - 1) * N, xf + (T - 1) * N, N * 8, hipMemcpyDeviceToDevice, s));
     if (Pdiag) HIPCK(diag_copy(p->Ps[(T - 1) & 1], ld, (int)N, Pdiag + (T - 1) * N, s));
     if (Pfull)
@@ -685,7 +692,7 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
     };
     if (p->stride == 1) {
         // Every P_{t|t} is stored: gains run one batch ahead on the side stream.
-        struct Batch { int count; int64_t ts[kMaxBatch]; const void* Pt[kMaxBatch]; };
+        struct Batch { int count; int64_t ts[kMaxBatch]; const void* Pt[kMaxBatch]; bool is32[kMaxBatch]; };
         std::vector<Batch> batches;
         for (int64_t t = T - 2; t >= 0;) {
             Batch bt;
@@ -693,6 +700,7 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
             while (bt.count < p->gbatch && t - bt.count >= 0) {
                 bt.ts[bt.count] = t - bt.count;
                 bt.Pt[bt.count] = slot_ptr(p, t - bt.count);
+                bt.is32[bt.count] = !slot64(p);
                 ++bt.count;
             }
             batches.push_back(bt);
@@ -702,14 +710,15 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
         HIPCK(hipStreamWaitEvent(p->s2, p->ev_start, 0));
         const size_t nb = batches.size();
         if (nb > 0) {
-            TRY(gain_batch(p, 0, batches[0].count, batches[0].ts, batches[0].Pt, p->s2));
+            TRY(gain_batch(p, 0, batches[0].count, batches[0].ts, batches[0].Pt, batches[0].is32, p->s2));
             HIPCK(hipEventRecord(p->ev_gain[0], p->s2));
         }
         for (size_t k = 0; k < nb; ++k) {
             if (k + 1 < nb) {
                 const int set = (int)((k + 1) & 1);
                 if (k >= 1) HIPCK(hipStreamWaitEvent(p->s2, p->ev_chain[set], 0));   // chain k-1 released it
-                TRY(gain_batch(p, set, batches[k + 1].count, batches[k + 1].ts, batches[k + 1].Pt, p->s2));
+                TRY(gain_batch(p, set, batches[k + 1].count, batches[k + 1].ts, batches[k + 1].Pt,
+                               batches[k + 1].is32, p->s2));
                 HIPCK(hipEventRecord(p->ev_gain[set], p->s2));
             }
             const int set = (int)(k & 1);
@@ -736,13 +745,15 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
             }
             int64_t ts[kMaxBatch];
             const void* Pt[kMaxBatch];
+            bool is32[kMaxBatch];
             int count = 0;
             while (count < p->gbatch && t - count >= 0 && stored(t - count)) {
                 ts[count] = t - count;
                 Pt[count] = stored(t - count);
+                is32[count] = kept(p, t - count, T) ? !slot64(p) : s32;   // checkpoints float64, segment as stored
                 ++count;
             }
-            TRY(gain_batch(p, 0, count, ts, Pt, s));
+            TRY(gain_batch(p, 0, count, ts, Pt, is32, s));
             TRY(run_chain(0, count, ts, Pt));
             t -= count;
         }
@@ -788,8 +799,11 @@ kf_status kf_get_filtered_cov(kf_plan* p, int64_t t, double* P_out) {
         const size_t esz = p->store32 ? 4 : 8;
         const void* src = static_cast<char*>(p->seg) + (size_t)(i - lo) * slot_elems(p) * esz;
         HIPCK(copy2d((int)p->N, (int)p->N, P_out, false, p->N, src, p->store32, p->ldN, p->stream));
+    } else if (p->store32) {       // the float32 store's value (a checkpoint is kept in float64)
+        HIPCK(copy2d_r32((int)p->N, (int)p->N, P_out, p->N, slot_ptr(p, slot_of(p, i, T)), !slot64(p), p->ldN,
+                         p->stream));
     } else {
-        HIPCK(copy2d((int)p->N, (int)p->N, P_out, false, p->N, slot_ptr(p, slot_of(p, i, T)), p->store32, p->ldN,
+        HIPCK(copy2d((int)p->N, (int)p->N, P_out, false, p->N, slot_ptr(p, slot_of(p, i, T)), false, p->ldN,
                      p->stream));
     }
     HIPCK(hipStreamSynchronize(p->stream));

@@ -94,6 +94,9 @@ hipError_t axpby3(int rows, int cols, void* D, bool d32, int64_t ldd,
 // copy rows x cols between (possibly) different precisions and leading dimensions
 hipError_t copy2d(int rows, int cols, void* dst, bool d32, int64_t ldd,
                   const void* src, bool s32, int64_t lds, hipStream_t s);
+// dst (float64) = src rounded to float32 (src float or double): what a float32 store would hold
+hipError_t copy2d_r32(int rows, int cols, double* dst, int64_t ldd, const void* src, bool s32, int64_t lds,
+                      hipStream_t s);
 // set a rows x cols block to zero
 hipError_t zero2d(int rows, int cols, double* dst, int64_t ldd, hipStream_t s);
 // scan n values for NaN / Inf; sets *flag = 1 if any

@@ -100,6 +100,15 @@ __global__ void copy2d_kernel(int rows, int cols, void* dst, bool d32, int64_t l
     }
 }
 
+__global__ void copy2d_r32_kernel(int rows, int cols, double* dst, int64_t ldd, const void* src, bool s32,
+                                  int64_t lds) {
+    const int64_t n = (int64_t)rows * cols;
+    for (int64_t idx = blockIdx.x * (int64_t)TPB + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * TPB) {
+        const int i = (int)(idx / cols), j = (int)(idx - (int64_t)i * cols);
+        dst[(int64_t)i * ldd + j] = (double)(float)ld_any(src, s32, (int64_t)i * lds + j);
+    }
+}
+
 __global__ void zero2d_kernel(int rows, int cols, double* dst, int64_t ldd) {
     const int64_t n = (int64_t)rows * cols;
     for (int64_t idx = blockIdx.x * (int64_t)TPB + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * TPB) {
@@ -184,6 +193,13 @@ hipError_t copy2d(int rows, int cols, void* dst, bool d32, int64_t ldd, const vo
                   hipStream_t s) {
     hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for((int64_t)rows * cols)), dim3(TPB), 0, s, rows, cols, dst, d32,
                        ldd, src, s32, lds);
+    return hipGetLastError();
+}
+
+hipError_t copy2d_r32(int rows, int cols, double* dst, int64_t ldd, const void* src, bool s32, int64_t lds,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(copy2d_r32_kernel, dim3(grid_for((int64_t)rows * cols)), dim3(TPB), 0, s, rows, cols, dst, ldd,
+                       src, s32, lds);
     return hipGetLastError();
 }
 

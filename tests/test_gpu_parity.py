@@ -92,10 +92,12 @@ def test_store_fp32_with_fp64_arithmetic():
     print("fp32 store errors", errs)
 
 
-def test_checkpoint_recompute_matches_store_all_bitwise():
+@pytest.mark.parametrize("opt", [{}, {"store_fp32": True}, {"precision": kfmeg.KF_MIXED, "store_fp32": True},
+                                 {"precision": kfmeg.KF_MIXED}])
+def test_checkpoint_recompute_matches_store_all_bitwise(opt):
     p = synth.tiny(T=23)
-    a, fa = gpu_run(p, full=True)
-    b, fb = gpu_run(p, full=True, checkpoint_stride=5)
+    a, fa = gpu_run(p, full=True, **opt)
+    b, fb = gpu_run(p, full=True, checkpoint_stride=5, **opt)
     for u, v in ((a.x_smooth, b.x_smooth), (a.Pdiag_smooth, b.Pdiag_smooth), (a.P_smooth, b.P_smooth)):
         assert torch.equal(u, v)
     assert all(np.array_equal(u, v) for u, v in zip(fa, fb))

@@ -240,6 +240,17 @@ def test_p10_calibration_chi_square():
     assert stats.kstest(zf, stats.chi2(N).cdf).pvalue > 1e-3
 
 
+# ---------------------------------------------------------------- sampled smoother step
+def test_rts_step_columns_matches_full_smoother():
+    p = synth.small_random(71, 30, 7, 5)
+    xf, Pf, dPf, xs, Ps, dPs = run(p)
+    cols = [0, 3, 17, 29]
+    for t in range(p.T - 1):
+        x_t, Pc = K.rts_step_columns(xf[t], Pf[t], xs[t + 1], Ps[t + 1], p.Q, cols)
+        assert rel(x_t, xs[t]) < 1e-12
+        assert rel(Pc, Ps[t][:, cols]) < 1e-12
+
+
 # ---------------------------------------------------------------- planted mistakes
 def _smooth_literal_eqn12(xf, Pf, Q):
     # The misprinted eqn12 taken literally: x_{t|T} = x_{t|t} + A (x_{t|t} - x_{t+1|t}) == x_{t|t}.
