@@ -102,6 +102,26 @@ kf_status kf_filter(kf_plan* plan, int64_t T, const double* Y,
 kf_status kf_smooth(kf_plan* plan, double* x_smooth, double* Pdiag_smooth,
                     double* P_smooth);
 
+/*
+ * kf_filter_batch / kf_smooth_batch: the same filter and smoother for B >= 1
+ * data sets that share the model (X, Q, R, x0, P0). The covariance recursion
+ * (eqn7-eqn9 and the update after eqn10, and eqn11, eqn13 in the smoother)
+ * does not involve the data, so it runs once and the B means advance together
+ * as B-row matrix products.
+ *   Y          (B x T x m) data, Y[b][t-1] = y_t of data set b
+ *   x_filt     (B x T x N) out: x_{t|t} of each data set
+ *   x_smooth   (B x T x N) out: x_{t|T} of each data set
+ *   Pdiag_*, P_smooth as for kf_filter / kf_smooth (shared by all data sets)
+ * kf_smooth_batch returns KF_ESTATE unless B equals the B of the last filter
+ * call on the plan; kf_filter and kf_smooth are the B = 1 case. Not available
+ * on plans owned by a serving context (KF_EINVAL). The plan allocates
+ * 2 B (m + N) doubles of workspace on the first call with a larger B.
+ */
+kf_status kf_filter_batch(kf_plan* plan, int64_t B, int64_t T, const double* Y,
+                          double* x_filt, double* Pdiag_filt);
+kf_status kf_smooth_batch(kf_plan* plan, int64_t B, double* x_smooth,
+                          double* Pdiag_smooth, double* P_smooth);
+
 /* Copy the stored filtered covariance P_{t|t} (1 <= t <= T) into P_out (N x N, device). */
 kf_status kf_get_filtered_cov(kf_plan* plan, int64_t t, double* P_out);
 
@@ -116,6 +136,20 @@ kf_status kf_get_filtered_cov(kf_plan* plan, int64_t t, double* P_out);
  */
 kf_status mne_solve(int64_t N, int64_t m, int64_t T, const double* X, const double* C,
                     const double* R, const double* Y, double* J, void* stream);
+
+/*
+ * kf_init_from_mne: the parameter set-up of Section 2.4. Computes the MNE
+ * estimates J_t (eqn5, prior covariance C) for every row of Y (T x m, T >= 3),
+ * returns x0_out = J_1 (the estimate of the first sample) and
+ *   Q_out = sample covariance of the differences J_t - J_{t-1}, t = 2..T
+ *           (divisor T - 2) + reg * I,
+ * an estimate of Sigma_w of rank at most T - 2 before the regulariser.
+ * x0_out (N) and Q_out (N x N, exactly symmetric) are device buffers the
+ * caller owns. Synchronises `stream` before it returns.
+ */
+kf_status kf_init_from_mne(int64_t N, int64_t m, int64_t T, const double* X, const double* C,
+                           const double* R, const double* Y, double reg, double* x0_out,
+                           double* Q_out, void* stream);
 
 /* Free a plan and everything it owns. NULL is accepted. */
 void kf_destroy(kf_plan* plan);

@@ -35,7 +35,8 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-__all__ = ["kf_update", "kf_filter", "smoother_gain", "rts_smooth", "rts_step_columns", "mne_solve"]
+__all__ = ["kf_update", "kf_filter", "smoother_gain", "rts_smooth", "rts_step_columns", "mne_solve",
+           "init_from_mne"]
 
 
 def _chol(A: np.ndarray):
@@ -144,3 +145,19 @@ def mne_solve(X, C, R, Y) -> np.ndarray:
     S = X @ G + R                                    # lambda H R H^T + Sigma_eps
     Z = sla.cho_solve(_chol(S), np.asarray(Y, dtype=np.float64).T)
     return (G @ Z).T
+
+
+def init_from_mne(X, C, R, Y, reg: float = 0.0):
+    """Initial state and process-noise covariance from MNE estimates (Section 2.4).
+
+    Reading: the initial state is the MNE estimate of the first data sample, and Sigma_w is
+    the sample covariance (divisor T-2) of the differenced sequence J_k - J_{k-1}, k = 2..T,
+    plus reg * I (the sample covariance has rank at most T-2). Returns (x0, Q).
+    """
+    J = mne_solve(X, C, R, Y)                        # eqn5 at every sample
+    D = J[1:] - J[:-1]
+    Dc = D - D.mean(axis=0)
+    Q = Dc.T @ Dc / (D.shape[0] - 1)
+    Q = (Q + Q.T) / 2.0
+    Q = Q + reg * np.eye(Q.shape[0])
+    return J[0].copy(), Q

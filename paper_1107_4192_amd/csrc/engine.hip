@@ -76,7 +76,12 @@ struct kf_plan {
     int* dstatus = nullptr;
     int* hstatus = nullptr;
     int64_t T_done = 0;
-    double* xf_last = nullptr;    // caller's x_filt of the last kf_filter call (for kf_smooth)
+    int64_t B_done = 1;           // data sets of the last filter call
+    double* xf_last = nullptr;    // caller's x_filt of the last filter call (for the smoother)
+    // several data sets through one covariance pass: the means of all data sets advance
+    // together as B-row products (buffers sized for bcap data sets, grown on demand)
+    int64_t bcap = 0;
+    double *Eb = nullptr, *Wb = nullptr, *Xb0 = nullptr, *Vb = nullptr;
     std::string err;
     // profiling of the smoother's N x N x N products (event pairs around each launch)
     bool prof = false;
@@ -261,6 +266,94 @@ kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* 
             HIPCK(gemm1(Dt::F64, g, s));
         }
     }
+    return KF_OK;
+}
+
+// Buffers for the means of B data sets (E, W: B x m residuals; Xb0: B copies of x0; Vb: B x N).
+kf_status ensure_batch(kf_plan* p, int64_t B) {
+    if (B <= p->bcap) return KF_OK;
+    if (p->arena) {
+        p->err = "several data sets per call are not available on a serving plan";
+        return KF_EINVAL;
+    }
+    for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb})
+        if (b) (void)hipFree(b);
+    p->Eb = p->Wb = p->Xb0 = p->Vb = nullptr;
+    p->bcap = 0;
+    const size_t bm = (size_t)B * p->ldm * 8, bn = (size_t)B * p->ldN * 8;
+    if (hipMalloc(&p->Eb, bm) != hipSuccess || hipMalloc(&p->Wb, bm) != hipSuccess ||
+        hipMalloc(&p->Xb0, bn) != hipSuccess || hipMalloc(&p->Vb, bn) != hipSuccess) {
+        (void)hipGetLastError();
+        p->err = "device allocation for " + std::to_string(B) + " data sets failed";
+        return KF_ENOMEM;
+    }
+    p->bcap = B;
+    return KF_OK;
+}
+
+// Split-K factor for a B-row product with K = N whose partial sums share the plan's buffer.
+int batch_ksplit(const kf_plan* p, int64_t rows, int64_t cols, int want) {
+    int k = want;
+    while (k > 1 && (size_t)k * rows * cols > p->partial_elems) k /= 2;
+    return k;
+}
+
+// Mean update of eqn10 for B data sets at once, after filter_cov_step(t) has left Li = L^{-1}
+// (of S_t) and C = Li X P_{t|t-1} in the plan: with E = Y_t - X_prev X^T (B x m),
+// X_t = X_prev + (E Li^T) C. Row b of X_prev / X_t is data set b's mean (leading dimension ldx).
+kf_status filter_mean_batch(kf_plan* p, int64_t B, const double* Xprev, int64_t ldprev, const double* Yt,
+                            int64_t ldy, double* Xt, int64_t ldx) {
+    hipStream_t s = p->stream;
+    const int N = (int)p->N, m = (int)p->m;
+    {
+        GemmProblem g;                       // E = Y_t - X_prev X^T
+        g.M = (int)B; g.N = m; g.K = N;
+        g.A = Xprev; g.lda = ldprev;
+        g.B = p->X; g.ldb = p->ldN; g.flags = G_TB;
+        g.alpha = -1.0;
+        g.Cin = Yt; g.ldcin = ldy; g.beta = 1.0;
+        g.C = p->Eb; g.ldc = p->ldm;
+        g.ksplit = batch_ksplit(p, B, m, std::max(1, std::min(16, N / 256)));
+        g.partial = p->partial;
+        HIPCK(gemm1(Dt::F64, g, s));
+    }
+    {
+        GemmProblem g;                       // W = E Li^T  (Li lower: W_b = Li e_b)
+        g.M = (int)B; g.N = m; g.K = m;
+        g.A = p->Eb; g.lda = p->ldm;
+        g.B = p->Lis; g.ldb = p->ldm; g.flags = G_TB;
+        g.C = p->Wb; g.ldc = p->ldm;
+        HIPCK(gemm1(Dt::F64, g, s));
+    }
+    {
+        GemmProblem g;                       // X_t = X_prev + W C
+        g.M = (int)B; g.N = N; g.K = m;
+        g.A = p->Wb; g.lda = p->ldm;
+        g.B = p->Cm; g.ldb = p->ldN;
+        g.Cin = Xprev; g.ldcin = ldprev; g.beta = 1.0;
+        g.C = Xt; g.ldc = ldx;
+        HIPCK(gemm1(Dt::F64, g, s));
+    }
+    return KF_OK;
+}
+
+// Smoothed means of eqn12 for B data sets: X_{t|T} = X_{t|t} + (X_{t+1|T} - X_{t|t}) A_t^T,
+// rows of the B x T x N arrays xf / xs (leading dimension T N).
+kf_status smooth_mean_batch(kf_plan* p, int64_t B, const double* A, int64_t t, const double* xf, double* xs) {
+    hipStream_t s = p->stream;
+    const int N = (int)p->N;
+    const int64_t ldx = p->T_done * N;
+    HIPCK(axpby3((int)B, N, p->Vb, false, p->ldN, xs + (t + 1) * N, false, ldx, xf + t * N, false, ldx, -1.0,
+                 nullptr, false, 0, 0.0, s));
+    GemmProblem g;
+    g.M = (int)B; g.N = N; g.K = N;
+    g.A = p->Vb; g.lda = p->ldN;
+    g.B = A; g.ldb = p->ldN; g.flags = G_TB;
+    g.Cin = xf + t * N; g.ldcin = ldx; g.beta = 1.0;
+    g.C = xs + t * N; g.ldc = ldx;
+    g.ksplit = batch_ksplit(p, B, N, 4);
+    g.partial = p->partial;
+    HIPCK(gemm1(Dt::F64, g, s));
     return KF_OK;
 }
 
@@ -502,26 +595,37 @@ kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const do
     return create_plan(out, N, m, T_max, X, Q, R, x0, P0, opt, stream, nullptr);
 }
 
-static kf_status filter_impl(kf_plan* p, int64_t T, const double* Y, double* x_filt, double* Pdiag) {
+static kf_status filter_impl(kf_plan* p, int64_t B, int64_t T, const double* Y, double* x_filt, double* Pdiag) {
     hipStream_t s = p->stream;
     const int64_t N = p->N, m = p->m;
     HIPCK(hipMemsetAsync(p->dstatus, 0, 4 * sizeof(int), s));
-    HIPCK(nonfinite_scan(Y, T * m, p->dstatus, s));
+    HIPCK(nonfinite_scan(Y, B * T * m, p->dstatus, s));
     HIPCK(hipMemcpyAsync(p->hstatus, p->dstatus, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     if (p->hstatus[0]) {
         p->err = "kf_filter: Y holds a non-finite value";
         return KF_EINVAL;
     }
-    HIPCK(hipMemcpyAsync(p->xw, p->x0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (B == 1) {
+        HIPCK(hipMemcpyAsync(p->xw, p->x0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+        TRY(ensure_batch(p, B));
+        HIPCK(copy2d((int)B, (int)N, p->Xb0, false, p->ldN, p->x0, false, 0, s));   // x0 in every row
+    }
     const bool direct = !p->store32 && p->stride == 1;   // store slot t is the working P
     const double* prev64 = p->P0;
     for (int64_t t = 0; t < T; ++t) {
         double* out64 = direct ? static_cast<double*>(slot_ptr(p, t)) : p->Pw[t & 1];
         float* out32 = nullptr;
         if (!slot64(p) && kept(p, t, T)) out32 = static_cast<float*>(slot_ptr(p, slot_of(p, t, T)));
-        TRY(filter_cov_step(p, t, prev64, out64, out32, Pdiag ? Pdiag + t * N : nullptr, Y + t * m,
-                            x_filt + t * N));
+        double* diag = Pdiag ? Pdiag + t * N : nullptr;
+        if (B == 1) {
+            TRY(filter_cov_step(p, t, prev64, out64, out32, diag, Y + t * m, x_filt + t * N));
+        } else {
+            TRY(filter_cov_step(p, t, prev64, out64, out32, diag, nullptr, nullptr));
+            const double* xprev = t == 0 ? p->Xb0 : x_filt + (t - 1) * N;
+            TRY(filter_mean_batch(p, B, xprev, t == 0 ? p->ldN : T * N, Y + t * m, T * m, x_filt + t * N, T * N));
+        }
         if (!direct && slot64(p) && kept(p, t, T)) {
             HIPCK(hipMemcpyAsync(slot_ptr(p, slot_of(p, t, T)), out64, slot_elems(p) * 8, hipMemcpyDeviceToDevice,
                                  s));
@@ -531,20 +635,25 @@ static kf_status filter_impl(kf_plan* p, int64_t T, const double* Y, double* x_f
     return sync_and_check(p, "kf_filter");
 }
 
-kf_status kf_filter(kf_plan* p, int64_t T, const double* Y, double* x_filt, double* Pdiag_filt) {
+kf_status kf_filter_batch(kf_plan* p, int64_t B, int64_t T, const double* Y, double* x_filt, double* Pdiag_filt) {
     if (!p) return KF_EINVAL;
     p->err.clear();
     p->T_done = 0;
-    if (T <= 0 || T > p->Tmax || !Y || !x_filt) {
-        p->err = "kf_filter: need 1 <= T <= T_max and non-null Y, x_filt";
+    if (B < 1 || T <= 0 || T > p->Tmax || !Y || !x_filt) {
+        p->err = "kf_filter: need B >= 1, 1 <= T <= T_max and non-null Y, x_filt";
         return KF_EINVAL;
     }
-    kf_status st = filter_impl(p, T, Y, x_filt, Pdiag_filt);
+    kf_status st = filter_impl(p, B, T, Y, x_filt, Pdiag_filt);
     if (st == KF_OK) {
         p->T_done = T;
+        p->B_done = B;
         p->xf_last = x_filt;
     }
     return st;
+}
+
+kf_status kf_filter(kf_plan* p, int64_t T, const double* Y, double* x_filt, double* Pdiag_filt) {
+    return kf_filter_batch(p, 1, T, Y, x_filt, Pdiag_filt);
 }
 
 }  // extern "C"
@@ -628,7 +737,8 @@ kf_status chain_step(kf_plan* p, int set, int b, int64_t t, const void* Pt, cons
     const double* Pt64 = p->store32 ? p->Pt64[set][b] : static_cast<const double*>(Pt);
     const double* A = p->Ab[set][b];
     // x_{t|T} = x_{t|t} + A_t (x_{t+1|T} - x_{t|t})   (eqn12, RTS reading)
-    HIPCK(gemv_smooth(A, ld, xf + t * N, xs + (t + 1) * N, xs + t * N, N, s));
+    if (p->B_done == 1) HIPCK(gemv_smooth(A, ld, xf + t * N, xs + (t + 1) * N, xs + t * N, N, s));
+    else TRY(smooth_mean_batch(p, p->B_done, A, t, xf, xs));
     if (mixed(p)) {
         // D = P_{t+1|T} - P_t - Q in float32; M = A D; P_{t|T} = P_t + M A^T   (eqn13)
         HIPCK(axpby3(N, N, p->D32, true, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
@@ -674,7 +784,8 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
     const void* PT = slot_ptr(p, slot_of(p, T - 1, T));
     if (s32) HIPCK(copy2d_r32((int)N, (int)N, p->Ps[(T - 1) & 1], ld, PT, !slot64(p), ld, s));
     else HIPCK(copy2d((int)N, (int)N, p->Ps[(T - 1) & 1], false, ld, PT, false, ld, s));
-    HIPCK(hipMemcpyAsync(xs + (T - 1) * N, xf + (T - 1) * N, N * 8, hipMemcpyDeviceToDevice, s));
+    HIPCK(hipMemcpy2DAsync(xs + (T - 1) * N, T * N * 8, xf + (T - 1) * N, T * N * 8, N * 8, p->B_done,
+                           hipMemcpyDeviceToDevice, s));
     if (Pdiag) HIPCK(diag_copy(p->Ps[(T - 1) & 1], ld, (int)N, Pdiag + (T - 1) * N, s));
     if (Pfull)
         HIPCK(hipMemcpy2DAsync(Pfull + (T - 1) * N * N, N * 8, p->Ps[(T - 1) & 1], ld * 8, N * 8, N,
@@ -767,11 +878,16 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
 
 extern "C" {
 
-kf_status kf_smooth(kf_plan* p, double* x_smooth, double* Pdiag_smooth, double* P_smooth) {
+kf_status kf_smooth_batch(kf_plan* p, int64_t B, double* x_smooth, double* Pdiag_smooth, double* P_smooth) {
     if (!p) return KF_EINVAL;
     p->err.clear();
     if (p->T_done <= 0 || !p->xf_last) {
         p->err = "kf_smooth: no completed kf_filter on this plan";
+        return KF_ESTATE;
+    }
+    if (B != p->B_done) {
+        p->err = "kf_smooth: the last filter call ran " + std::to_string(p->B_done) + " data set(s), not " +
+                 std::to_string(B);
         return KF_ESTATE;
     }
     if (!x_smooth) {
@@ -779,6 +895,10 @@ kf_status kf_smooth(kf_plan* p, double* x_smooth, double* Pdiag_smooth, double* 
         return KF_EINVAL;
     }
     return smooth_impl(p, x_smooth, Pdiag_smooth, P_smooth);
+}
+
+kf_status kf_smooth(kf_plan* p, double* x_smooth, double* Pdiag_smooth, double* P_smooth) {
+    return kf_smooth_batch(p, 1, x_smooth, Pdiag_smooth, P_smooth);
 }
 
 kf_status kf_get_filtered_cov(kf_plan* p, int64_t t, double* P_out) {
@@ -838,6 +958,8 @@ void kf_destroy(kf_plan* p) {
     for (hipEvent_t e : {p->ev_start, p->ev_gain[0], p->ev_gain[1], p->ev_chain[0], p->ev_chain[1]})
         if (e) (void)hipEventDestroy(e);
     if (p->s2) (void)hipStreamDestroy(p->s2);
+    for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb})
+        if (b) (void)hipFree(b);
     for (void* a : p->allocs) {
         if (p->arena) p->arena->release(a);
         else (void)hipFree(a);
@@ -924,6 +1046,42 @@ kf_status mne_solve(int64_t N, int64_t m, int64_t T, const double* X, const doub
     st = run();
     if (st != KF_OK) g_err = tmp.err;
     return cleanup(st);
+}
+
+kf_status kf_init_from_mne(int64_t N, int64_t m, int64_t T, const double* X, const double* C, const double* R,
+                           const double* Y, double reg, double* x0_out, double* Q_out, void* stream) {
+    g_err.clear();
+    if (N <= 0 || m <= 0 || T < 3 || !X || !C || !R || !Y || !x0_out || !Q_out || !(reg >= 0.0)) {
+        g_err = "kf_init_from_mne: need N, m > 0, T >= 3, reg >= 0 and non-null pointers";
+        return KF_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    kf_plan tmp;
+    kf_plan* p = &tmp;
+    const int64_t ld = round_up(N, 16);
+    double *J = nullptr, *Dc = nullptr;
+    kf_status st = alloc(p, &J, (size_t)T * N);
+    if (st == KF_OK) st = alloc(p, &Dc, (size_t)(T - 1) * ld);
+    auto run = [&]() -> kf_status {
+        kf_status r = mne_solve(N, m, T, X, C, R, Y, J, stream);           // eqn5 at every sample
+        if (r != KF_OK) return r;
+        HIPCK(diff_center(J, N, (int)T, (int)N, Dc, ld, s));               // J_k - J_{k-1}, centred
+        GemmProblem g;                                                      // Dc^T Dc / (T - 2)
+        g.M = (int)N; g.N = (int)N; g.K = (int)(T - 1);
+        g.A = Dc; g.lda = ld; g.B = Dc; g.ldb = ld; g.flags = G_TA | G_LOWER | G_MIRROR;
+        g.alpha = 1.0 / (double)(T - 2);
+        g.C = Q_out; g.ldc = N;
+        HIPCK(gemm1(Dt::F64, g, s));
+        if (reg > 0.0) HIPCK(add_diag(Q_out, N, (int)N, reg, s));
+        HIPCK(hipMemcpyAsync(x0_out, J, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCK(hipStreamSynchronize(s));
+        return KF_OK;
+    };
+    if (st == KF_OK) st = run();
+    if (st != KF_OK && g_err.empty()) g_err = tmp.err;
+    for (void* a : tmp.allocs) (void)hipFree(a);
+    tmp.allocs.clear();
+    return st;
 }
 
 }  // extern "C"

@@ -97,6 +97,10 @@ hipError_t copy2d(int rows, int cols, void* dst, bool d32, int64_t ldd,
 // dst (float64) = src rounded to float32 (src float or double): what a float32 store would hold
 hipError_t copy2d_r32(int rows, int cols, double* dst, int64_t ldd, const void* src, bool s32, int64_t lds,
                       hipStream_t s);
+// centred first differences of the rows of J (T x N) into Dc ((T-1) x N)
+hipError_t diff_center(const double* J, int64_t ldj, int T, int N, double* Dc, int64_t ldd, hipStream_t s);
+// A[i][i] += v
+hipError_t add_diag(double* A, int64_t lda, int n, double v, hipStream_t s);
 // set a rows x cols block to zero
 hipError_t zero2d(int rows, int cols, double* dst, int64_t ldd, hipStream_t s);
 // scan n values for NaN / Inf; sets *flag = 1 if any

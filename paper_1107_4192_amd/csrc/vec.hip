@@ -109,6 +109,21 @@ __global__ void copy2d_r32_kernel(int rows, int cols, double* dst, int64_t ldd, 
     }
 }
 
+// Dc[k][j] = (J[k+1][j] - J[k][j]) - mean_k(J[k+1][j] - J[k][j]), k < T-1; one thread per column.
+__global__ void diff_center_kernel(const double* J, int64_t ldj, int T, int N, double* Dc, int64_t ldd) {
+    const int j = blockIdx.x * TPB + threadIdx.x;
+    if (j >= N) return;
+    double s = 0.0;
+    for (int k = 0; k + 1 < T; ++k) s += J[(int64_t)(k + 1) * ldj + j] - J[(int64_t)k * ldj + j];
+    const double mean = s / (double)(T - 1);
+    for (int k = 0; k + 1 < T; ++k) Dc[(int64_t)k * ldd + j] = (J[(int64_t)(k + 1) * ldj + j] - J[(int64_t)k * ldj + j]) - mean;
+}
+
+__global__ void add_diag_kernel(double* A, int64_t lda, int n, double v) {
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    if (i < n) A[(int64_t)i * lda + i] += v;
+}
+
 __global__ void zero2d_kernel(int rows, int cols, double* dst, int64_t ldd) {
     const int64_t n = (int64_t)rows * cols;
     for (int64_t idx = blockIdx.x * (int64_t)TPB + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * TPB) {
@@ -200,6 +215,16 @@ hipError_t copy2d_r32(int rows, int cols, double* dst, int64_t ldd, const void* 
                       hipStream_t s) {
     hipLaunchKernelGGL(copy2d_r32_kernel, dim3(grid_for((int64_t)rows * cols)), dim3(TPB), 0, s, rows, cols, dst, ldd,
                        src, s32, lds);
+    return hipGetLastError();
+}
+
+hipError_t diff_center(const double* J, int64_t ldj, int T, int N, double* Dc, int64_t ldd, hipStream_t s) {
+    hipLaunchKernelGGL(diff_center_kernel, dim3((N + TPB - 1) / TPB), dim3(TPB), 0, s, J, ldj, T, N, Dc, ldd);
+    return hipGetLastError();
+}
+
+hipError_t add_diag(double* A, int64_t lda, int n, double v, hipStream_t s) {
+    hipLaunchKernelGGL(add_diag_kernel, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, A, lda, n, v);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ _STATUS = {0: "KF_OK", 1: "KF_EINVAL", 2: "KF_ENOTPD", 3: "KF_ENOMEM", 4: "KF_EH
 EXPORTS = ("kf_default_options", "kf_create", "kf_filter", "kf_smooth", "kf_get_filtered_cov",
            "mne_solve", "kf_destroy", "kf_last_error", "kf_plan_bytes", "kfd_gemm", "kfd_chol_inv", "kf_set_profiling", "kf_get_profile",
            "kfs_create", "kfs_submit", "kfs_wait", "kfs_job_info", "kfs_get_stats", "kfs_last_error",
-           "kfs_destroy")
+           "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch")
 
 
 class KFError(RuntimeError):
@@ -69,6 +69,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_filter.restype = ctypes.c_int
     lib.kf_smooth.argtypes = [vp, dp, dp, dp]
     lib.kf_smooth.restype = ctypes.c_int
+    lib.kf_filter_batch.argtypes = [vp, i64, i64, dp, dp, dp]
+    lib.kf_filter_batch.restype = ctypes.c_int
+    lib.kf_smooth_batch.argtypes = [vp, i64, dp, dp, dp]
+    lib.kf_smooth_batch.restype = ctypes.c_int
     lib.kf_get_filtered_cov.argtypes = [vp, i64, dp]
     lib.kf_get_filtered_cov.restype = ctypes.c_int
     lib.mne_solve.argtypes = [i64, i64, i64, dp, dp, dp, dp, dp, vp]
@@ -84,6 +88,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64)]
     lib.kf_get_profile.restype = ctypes.c_int
+    lib.kf_init_from_mne.argtypes = [i64, i64, i64, dp, dp, dp, dp, ctypes.c_double, dp, dp, vp]
+    lib.kf_init_from_mne.restype = ctypes.c_int
     lib.kfs_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(kf_options)]
     lib.kfs_create.restype = ctypes.c_int
     lib.kfs_submit.argtypes = [vp, i64, i64, i64, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(i64)]
@@ -178,6 +184,25 @@ def kf_smooth(plan: int, x_smooth, Pdiag_smooth=None, P_smooth=None) -> None:
     _check(lib, st, plan)
 
 
+def kf_filter_batch(plan: int, Y, x_filt, Pdiag_filt=None) -> None:
+    """Y: (B, T, m), x_filt: (B, T, N); the covariance pass is shared by the B data sets."""
+    lib = load_library()
+    B, T, m = Y.shape
+    N = x_filt.shape[2]
+    st = lib.kf_filter_batch(plan, B, T, _dev(Y, "Y", (B, T, m)), _dev(x_filt, "x_filt", (B, T, N)),
+                             _dev(Pdiag_filt, "Pdiag_filt", (T, N)) if Pdiag_filt is not None else None)
+    _check(lib, st, plan)
+
+
+def kf_smooth_batch(plan: int, x_smooth, Pdiag_smooth=None, P_smooth=None) -> None:
+    lib = load_library()
+    B, T, N = x_smooth.shape
+    st = lib.kf_smooth_batch(plan, B, _dev(x_smooth, "x_smooth", (B, T, N)),
+                             _dev(Pdiag_smooth, "Pdiag_smooth", (T, N)) if Pdiag_smooth is not None else None,
+                             _dev(P_smooth, "P_smooth", (T, N, N)) if P_smooth is not None else None)
+    _check(lib, st, plan)
+
+
 def kf_get_filtered_cov(plan: int, t: int, P_out) -> None:
     lib = load_library()
     N = P_out.shape[0]
@@ -215,6 +240,20 @@ def mne_solve(X, C, R, Y, J=None, stream=None):
                        _dev(Y, "Y", (T, m)), _dev(J, "J", (T, N)), _stream_ptr(stream))
     _check(lib, st, None)
     return J
+
+
+def kf_init_from_mne(X, C, R, Y, reg: float = 0.0, stream=None):
+    """Section 2.4 set-up: (x0, Q) from MNE estimates of every sample of Y."""
+    lib = load_library()
+    _need_gpu()
+    m, N = X.shape
+    T = Y.shape[0]
+    x0 = torch.empty(N, dtype=torch.float64, device=X.device)
+    Q = torch.empty((N, N), dtype=torch.float64, device=X.device)
+    st = lib.kf_init_from_mne(N, m, T, _dev(X, "X", (m, N)), _dev(C, "C", (N, N)), _dev(R, "R", (m, m)),
+                              _dev(Y, "Y", (T, m)), float(reg), x0.data_ptr(), Q.data_ptr(), _stream_ptr(stream))
+    _check(lib, st, None)
+    return x0, Q
 
 
 # ---------------------------------------------------------------- serving
@@ -352,6 +391,18 @@ class KalmanSmoother:
 
     def run(self, Y, want_full: bool = False) -> Result:
         return self.smooth(self.filter(Y), want_full=want_full)
+
+    def run_batch(self, Y, want_diag: bool = True) -> Result:
+        """Filter and smooth B data sets, Y: (B, T, m); means come back as (B, T, N)."""
+        B, T, _ = Y.shape
+        dev = Y.device
+        res = Result(torch.empty((B, T, self.N), dtype=torch.float64, device=dev),
+                     torch.empty((T, self.N), dtype=torch.float64, device=dev) if want_diag else None)
+        kf_filter_batch(self.plan, Y, res.x_filt, res.Pdiag_filt)
+        res.x_smooth = torch.empty((B, T, self.N), dtype=torch.float64, device=dev)
+        res.Pdiag_smooth = torch.empty((T, self.N), dtype=torch.float64, device=dev) if want_diag else None
+        kf_smooth_batch(self.plan, res.x_smooth, res.Pdiag_smooth)
+        return res
 
     def filtered_cov(self, t: int) -> torch.Tensor:
         P = torch.empty((self.N, self.N), dtype=torch.float64, device="cuda")

@@ -240,6 +240,34 @@ def test_p10_calibration_chi_square():
     assert stats.kstest(zf, stats.chi2(N).cdf).pvalue > 1e-3
 
 
+# ---------------------------------------------------------------- Section 2.4 set-up
+def test_init_from_mne_matches_outer_product_sum():
+    rng = np.random.default_rng(81)
+    N, m, T = 9, 4, 12
+    X = rng.normal(size=(m, N)); C = 0.5 * np.eye(N); R = synth.random_spd(rng, m, 3.0, 0.1)
+    Y = rng.normal(size=(T, m))
+    x0, Q = oracle.init_from_mne(X, C, R, Y, reg=1e-3)
+    J = oracle.mne_solve(X, C, R, Y)
+    assert np.array_equal(x0, J[0])
+    d = [J[k] - J[k - 1] for k in range(1, T)]
+    dbar = sum(d) / len(d)
+    S = sum(np.outer(v - dbar, v - dbar) for v in d) / (len(d) - 1) + 1e-3 * np.eye(N)
+    assert rel(Q, S) < 1e-12
+    assert np.linalg.eigvalsh(Q).min() >= 1e-3 * (1 - 1e-9)
+
+
+def test_init_from_mne_recovers_random_walk_covariance():
+    # With X = I and tiny sensor noise, MNE estimates are the states, and the differences are
+    # the process noise: the estimate converges to Q.
+    rng = np.random.default_rng(82)
+    N, T = 3, 20000
+    Qt = np.array([[0.5, 0.1, 0.0], [0.1, 0.3, 0.05], [0.0, 0.05, 0.2]])
+    w = rng.multivariate_normal(np.zeros(N), Qt, size=T)
+    Y = np.cumsum(w, axis=0)
+    x0, Q = oracle.init_from_mne(np.eye(N), 1e6 * np.eye(N), 1e-9 * np.eye(N), Y)
+    assert np.abs(Q - Qt).max() < 0.02
+
+
 # ---------------------------------------------------------------- sampled smoother step
 def test_rts_step_columns_matches_full_smoother():
     p = synth.small_random(71, 30, 7, 5)
