@@ -168,6 +168,86 @@ __device__ __forceinline__ void tri_decode(int t, int& bm, int& bn) {
     bn = t - r * (r + 1) / 2;
 }
 
+// c[b][r] = src(ii, jj) as float64 for the 16 elements of one strip (element 0 where !ok).
+__device__ __forceinline__ void gather_strip(double (&c)[4][4], const void* src, bool f32, int64_t ld,
+                                             const int (&ii)[4][4], const int (&jj)[4][4], const bool (&ok)[4][4]) {
+    if (f32) {
+        const float* p = static_cast<const float*>(src);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) c[b][r] = (double)p[ok[b][r] ? (int64_t)ii[b][r] * ld + jj[b][r] : 0];
+    } else {
+        const double* p = static_cast<const double*>(src);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) c[b][r] = p[ok[b][r] ? (int64_t)ii[b][r] * ld + jj[b][r] : 0];
+    }
+}
+
+// Result of one tile: raw partial sums (split-K), or C = alpha acc + beta Cin + gamma Cin2
+// with the lower / mirror / diagonal / float32 options. Lane (lk, lr) of wave (wm, wn) holds
+// acc[a][b][r] = C(i0 + wm + 16a + row(lk, r), j0 + wn + 16b + lr).
+template <typename T>
+__device__ __forceinline__ void epilogue(const GemmProblem& P, const typename Acc<T>::V (&acc)[4][4], int i0,
+                                         int j0, int split, int tid) {
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int lr = lane & 15, lk = lane >> 4;
+    if (P.ksplit > 1) {
+        T* part = static_cast<T*>(P.partial) + (int64_t)split * P.M * P.N;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + wm + 16 * a + Acc<T>::row(lk, r), j = j0 + wn + 16 * b + lr;
+                    if (i < P.M && j < P.N) part[(int64_t)i * P.N + j] = acc[a][b][r];
+                }
+        return;
+    }
+    const bool lower = P.flags & G_LOWER, mirror = P.flags & G_MIRROR;
+    const bool cin32 = P.flags & G_CIN32, cin2_32 = P.flags & G_CIN2_32;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        // The strip's Cin / Cin2 values are all loaded before any store: C may alias Cin
+        // (in-place updates), so a load that follows a store in program order could not be
+        // hoisted above it, and every element would pay a full memory round trip in turn.
+        int ii[4][4], jj[4][4];
+        bool ok[4][4];
+        double c1[4][4], c2[4][4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ii[b][r] = i0 + wm + 16 * a + Acc<T>::row(lk, r);
+                jj[b][r] = j0 + wn + 16 * b + lr;
+                ok[b][r] = ii[b][r] < P.M && jj[b][r] < P.N && !(lower && jj[b][r] > ii[b][r]);
+            }
+        if (P.Cin) gather_strip(c1, P.Cin, cin32, P.ldcin, ii, jj, ok);
+        if (P.Cin2) gather_strip(c2, P.Cin2, cin2_32, P.ldcin2, ii, jj, ok);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (!ok[b][r]) continue;
+                const int i = ii[b][r], j = jj[b][r];
+                double v = P.alpha * (double)acc[a][b][r];
+                if (P.Cin) v += P.beta * c1[b][r];
+                if (P.Cin2) v += P.gamma * c2[b][r];
+                if (P.C) P.C[(int64_t)i * P.ldc + j] = v;
+                if (P.C32) P.C32[(int64_t)i * P.ldc32 + j] = (float)v;
+                if (P.diag && i == j) P.diag[i] = v;
+                if (mirror && i > j) {
+                    if (P.C) P.C[(int64_t)j * P.ldc + i] = v;
+                    if (P.C32) P.C32[(int64_t)j * P.ldc32 + i] = (float)v;
+                }
+            }
+    }
+}
+
 // Generic path: any alignment or leading dimension, B-operand addends; branchy loads.
 template <typename T>
 __global__ __launch_bounds__(NT) void gemm_generic_kernel(GemmGroup G) {
@@ -255,42 +335,7 @@ __global__ __launch_bounds__(NT) void gemm_generic_kernel(GemmGroup G) {
         }
     }
 
-    // ---- epilogue. Lane holds acc[a][b][r] = C(i0+wm+16a+row(lk,r), j0+wn+16b+lr).
-    if (P.ksplit > 1) {
-        T* part = static_cast<T*>(P.partial) + (int64_t)split * P.M * P.N;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = i0 + wm + 16 * a + Acc<T>::row(lk, r), j = j0 + wn + 16 * b + lr;
-                    if (i < P.M && j < P.N) part[(int64_t)i * P.N + j] = acc[a][b][r];
-                }
-        return;
-    }
-    const bool lower = P.flags & G_LOWER, mirror = P.flags & G_MIRROR;
-    const bool cin32 = P.flags & G_CIN32, cin2_32 = P.flags & G_CIN2_32;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wm + 16 * a + Acc<T>::row(lk, r), j = j0 + wn + 16 * b + lr;
-                if (i >= P.M || j >= P.N) continue;
-                if (lower && j > i) continue;
-                double v = P.alpha * (double)acc[a][b][r];
-                if (P.Cin) v += P.beta * load_any(P.Cin, cin32, (int64_t)i * P.ldcin + j);
-                if (P.Cin2) v += P.gamma * load_any(P.Cin2, cin2_32, (int64_t)i * P.ldcin2 + j);
-                if (P.C) P.C[(int64_t)i * P.ldc + j] = v;
-                if (P.C32) P.C32[(int64_t)i * P.ldc32 + j] = (float)v;
-                if (P.diag && i == j) P.diag[i] = v;
-                if (mirror && i > j) {
-                    if (P.C) P.C[(int64_t)j * P.ldc + i] = v;
-                    if (P.C32) P.C32[(int64_t)j * P.ldc32 + i] = (float)v;
-                }
-            }
+    epilogue<T>(P, acc, i0, j0, split, tid);
 }
 
 // Split-K reduction in fixed split order (deterministic), then the epilogue.
@@ -399,49 +444,6 @@ struct Operand {
         }
     }
 };
-
-template <typename T>
-__device__ __forceinline__ void epilogue(const GemmProblem& P, const typename Acc<T>::V (&acc)[4][4], int i0,
-                                         int j0, int split, int tid) {
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-    const int lr = lane & 15, lk = lane >> 4;
-    if (P.ksplit > 1) {
-        T* part = static_cast<T*>(P.partial) + (int64_t)split * P.M * P.N;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = i0 + wm + 16 * a + Acc<T>::row(lk, r), j = j0 + wn + 16 * b + lr;
-                    if (i < P.M && j < P.N) part[(int64_t)i * P.N + j] = acc[a][b][r];
-                }
-        return;
-    }
-    const bool lower = P.flags & G_LOWER, mirror = P.flags & G_MIRROR;
-    const bool cin32 = P.flags & G_CIN32, cin2_32 = P.flags & G_CIN2_32;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wm + 16 * a + Acc<T>::row(lk, r), j = j0 + wn + 16 * b + lr;
-                if (i >= P.M || j >= P.N) continue;
-                if (lower && j > i) continue;
-                double v = P.alpha * (double)acc[a][b][r];
-                if (P.Cin) v += P.beta * load_any(P.Cin, cin32, (int64_t)i * P.ldcin + j);
-                if (P.Cin2) v += P.gamma * load_any(P.Cin2, cin2_32, (int64_t)i * P.ldcin2 + j);
-                if (P.C) P.C[(int64_t)i * P.ldc + j] = v;
-                if (P.C32) P.C32[(int64_t)i * P.ldc32 + j] = (float)v;
-                if (P.diag && i == j) P.diag[i] = v;
-                if (mirror && i > j) {
-                    if (P.C) P.C[(int64_t)j * P.ldc + i] = v;
-                    if (P.C32) P.C32[(int64_t)j * P.ldc32 + i] = (float)v;
-                }
-            }
-}
 
 template <typename T, bool TA, bool TB>
 __device__ __forceinline__ void fast_tile(const GemmProblem& P, int bm, int bn, int split, T* As, T* Bs) {
