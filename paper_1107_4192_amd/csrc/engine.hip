@@ -808,7 +808,9 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
         for (int64_t t = T - 2; t >= 0;) {
             Batch bt;
             bt.count = 0;
-            while (bt.count < p->gbatch && t - bt.count >= 0) {
+            // a short first batch lets the back-recursion start early; later batches are full
+            const int cap = batches.empty() ? std::min(p->gbatch, 2) : p->gbatch;
+            while (bt.count < cap && t - bt.count >= 0) {
                 bt.ts[bt.count] = t - bt.count;
                 bt.Pt[bt.count] = slot_ptr(p, t - bt.count);
                 bt.is32[bt.count] = !slot64(p);

@@ -125,20 +125,6 @@ __device__ __forceinline__ void fetch_b(T (&r)[8], const GemmProblem& P, int j0,
     const bool tb = P.flags & G_TB;
     const bool vec = !(P.flags & G_SCALAR);
     fetch_b_one<T>(r, static_cast<const T*>(P.B), P.ldb, tb, P, j0, k0, khi, tid, vec);
-    if (P.B2) {
-        T r2[8];
-        fetch_b_one<T>(r2, static_cast<const T*>(P.B2), P.ldb2, tb, P, j0, k0, khi, tid, vec);
-        const T c = (T)P.b2coef;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) r[q] += c * r2[q];
-    }
-    if (P.B3) {
-        T r3[8];
-        fetch_b_one<T>(r3, static_cast<const T*>(P.B3), P.ldb3, tb, P, j0, k0, khi, tid, vec);
-        const T c = (T)P.b3coef;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) r[q] += c * r3[q];
-    }
 }
 
 // Write the staged registers into the [k][row] LDS tile.
@@ -248,7 +234,7 @@ __device__ __forceinline__ void epilogue(const GemmProblem& P, const typename Ac
     }
 }
 
-// Generic path: any alignment or leading dimension, B-operand addends; branchy loads.
+// Generic path: any alignment or leading dimension; branchy loads.
 template <typename T>
 __global__ __launch_bounds__(NT) void gemm_generic_kernel(GemmGroup G) {
     __shared__ T As[2][BK * BM];
@@ -599,10 +585,8 @@ hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s) {
         if ((p.flags & G_LOWER) && p.M != p.N) return hipErrorInvalidValue;
         const bool ta = p.flags & G_TA, tb = p.flags & G_TB;
         bool vec = aligned16(p.A) && aligned16(p.B) && p.lda % vec_elems == 0 && p.ldb % vec_elems == 0;
-        if (p.B2) vec = vec && aligned16(p.B2) && p.ldb2 % vec_elems == 0;
-        if (p.B3) vec = vec && aligned16(p.B3) && p.ldb3 % vec_elems == 0;
         if (!vec) p.flags |= G_SCALAR;
-        fast = fast && !p.B2 && !p.B3 && p.K > 0 && fast_ok(p.A, p.lda, ta ? p.M : p.K) &&
+        fast = fast && p.K > 0 && fast_ok(p.A, p.lda, ta ? p.M : p.K) &&
                fast_ok(p.B, p.ldb, tb ? p.K : p.N);
         p.tile_begin = total;
         const int tiles = (p.flags & G_LOWER) ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;

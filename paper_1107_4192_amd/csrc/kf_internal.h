@@ -9,7 +9,7 @@
 namespace kfmeg {
 
 // ---------------------------------------------------------------- GEMM
-// C = alpha * op(A) op(B) + beta * Cin + gamma * Cin2, with op(B) = B + b2coef B2 + b3coef B3.
+// C = alpha * op(A) op(B) + beta * Cin + gamma * Cin2.
 // Operands are of the kernel's compute type (double or float); the epilogue is float64.
 enum GemmFlags : int {
     G_TA = 1,          // A(i,k) = A[k*lda + i]   (else A[i*lda + k])
@@ -29,8 +29,6 @@ struct GemmProblem {
     int M = 0, N = 0, K = 0, flags = 0;
     const void* A = nullptr; int64_t lda = 0;
     const void* B = nullptr; int64_t ldb = 0;
-    const void* B2 = nullptr; int64_t ldb2 = 0; double b2coef = 0.0;
-    const void* B3 = nullptr; int64_t ldb3 = 0; double b3coef = 0.0;
     double alpha = 1.0, beta = 0.0, gamma = 0.0;
     const void* Cin = nullptr; int64_t ldcin = 0;
     const void* Cin2 = nullptr; int64_t ldcin2 = 0;
@@ -43,8 +41,8 @@ struct GemmProblem {
     int tiles_m = 0, tiles_n = 0, tile_begin = 0;
 };
 
-constexpr int kMaxGroup = 8;
-constexpr int kMaxBatch = 4;   // matrices per batched factorisation (two problems each per group)
+constexpr int kMaxGroup = 16;
+constexpr int kMaxBatch = 8;   // matrices per batched factorisation (two problems each per group)
 struct GemmGroup {
     GemmProblem p[kMaxGroup];
     int count = 0;
