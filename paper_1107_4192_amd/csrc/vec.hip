@@ -45,68 +45,82 @@ __global__ void trmv_lower_kernel(const double* L, int64_t ldl, const double* e,
     if (lane == 0) w[row] = s;
 }
 
-// x_out_j = x_in_j + sum_i C[i][j] w_i
-__global__ void gemv_t_add_kernel(const double* C, int64_t ldc, const double* w, const double* x_in,
-                                  double* x_out, double* x_copy, int m, int N) {
-    const int j = blockIdx.x * TPB + threadIdx.x;
-    if (j >= N) return;
+// x_out_j = x_in_j + sum_i C[i][j] w_i. A block covers 32 columns with 8 row groups
+// (rows g, g+8, ...); the 8 partial sums are added in a fixed order (deterministic).
+constexpr int GT_COLS = 32, GT_GROUPS = TPB / GT_COLS;
+__global__ __launch_bounds__(TPB) void gemv_t_add_kernel(const double* C, int64_t ldc, const double* w,
+                                                         const double* x_in, double* x_out, double* x_copy, int m,
+                                                         int N) {
+    __shared__ double part[GT_GROUPS][GT_COLS];
+    const int c = threadIdx.x % GT_COLS, g = threadIdx.x / GT_COLS;
+    const int j = blockIdx.x * GT_COLS + c;
     double s = 0.0;
-    for (int i = 0; i < m; ++i) s += C[(int64_t)i * ldc + j] * w[i];
-    const double v = x_in[j] + s;
-    x_out[j] = v;
-    if (x_copy) x_copy[j] = v;
+    if (j < N)
+        for (int i = g; i < m; i += GT_GROUPS) s += C[(int64_t)i * ldc + j] * w[i];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && j < N) {
+        double t = part[0][c];
+#pragma unroll
+        for (int q = 1; q < GT_GROUPS; ++q) t += part[q][c];
+        const double v = x_in[j] + t;
+        x_out[j] = v;
+        if (x_copy) x_copy[j] = v;
+    }
 }
 
-// out_i = x_i + sum_k A[i][k] (v_k - x_k)
+// out_i = x_i + sum_k A[i][k] (v_k - x_k); one wave per row, four interleaved partial sums
+// per lane so that four loads are in flight, combined in a fixed order.
 __global__ void gemv_smooth_kernel(const double* A, int64_t lda, const double* x, const double* v, double* out,
                                    int N) {
     const int row = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= N) return;
     const double* ar = A + (int64_t)row * lda;
-    double s = 0.0;
-    for (int k = lane; k < N; k += 64) s += ar[k] * (v[k] - x[k]);
-    s = wave_sum(s);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = lane;
+    for (; k + 192 < N; k += 256) {
+        s0 += ar[k] * (v[k] - x[k]);
+        s1 += ar[k + 64] * (v[k + 64] - x[k + 64]);
+        s2 += ar[k + 128] * (v[k + 128] - x[k + 128]);
+        s3 += ar[k + 192] * (v[k + 192] - x[k + 192]);
+    }
+    for (; k < N; k += 64) s0 += ar[k] * (v[k] - x[k]);
+    double s = wave_sum((s0 + s1) + (s2 + s3));
     if (lane == 0) out[row] = x[row] + s;
 }
 
-__device__ __forceinline__ double ld_any(const void* p, bool f32, int64_t idx) {
-    return f32 ? (double)static_cast<const float*>(p)[idx] : static_cast<const double*>(p)[idx];
-}
-__device__ __forceinline__ void st_any(void* p, bool f32, int64_t idx, double v) {
-    if (f32) static_cast<float*>(p)[idx] = (float)v;
-    else static_cast<double*>(p)[idx] = v;
-}
-
-__global__ void axpby3_kernel(int rows, int cols, void* D, bool d32, int64_t ldd, const void* a, bool a32,
-                              int64_t lda, const void* b, bool b32, int64_t ldb, double cb, const void* c,
-                              bool c32, int64_t ldc, double cc) {
-    const int64_t n = (int64_t)rows * cols;
-    for (int64_t idx = blockIdx.x * (int64_t)TPB + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * TPB) {
-        const int i = (int)(idx / cols), j = (int)(idx - (int64_t)i * cols);
-        double v = ld_any(a, a32, (int64_t)i * lda + j);
-        if (b) v += cb * ld_any(b, b32, (int64_t)i * ldb + j);
-        if (c) v += cc * ld_any(c, c32, (int64_t)i * ldc + j);
-        st_any(D, d32, (int64_t)i * ldd + j, v);
-    }
+// Elementwise sweeps over a rows x cols block: blockIdx.y walks the rows, the x dimension
+// the columns, so consecutive lanes touch consecutive elements and no index is divided.
+template <typename TD, typename TA, typename TB, typename TC>
+__global__ void axpby3_kernel(int rows, int cols, TD* D, int64_t ldd, const TA* a, int64_t lda, const TB* b,
+                              int64_t ldb, double cb, const TC* c, int64_t ldc, double cc) {
+    for (int i = blockIdx.y; i < rows; i += gridDim.y)
+        for (int j = blockIdx.x * TPB + threadIdx.x; j < cols; j += gridDim.x * TPB) {
+            double v = (double)a[(int64_t)i * lda + j];
+            if (b) v += cb * (double)b[(int64_t)i * ldb + j];
+            if (c) v += cc * (double)c[(int64_t)i * ldc + j];
+            D[(int64_t)i * ldd + j] = (TD)v;
+        }
 }
 
-__global__ void copy2d_kernel(int rows, int cols, void* dst, bool d32, int64_t ldd, const void* src, bool s32,
-                              int64_t lds) {
-    const int64_t n = (int64_t)rows * cols;
-    for (int64_t idx = blockIdx.x * (int64_t)TPB + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * TPB) {
-        const int i = (int)(idx / cols), j = (int)(idx - (int64_t)i * cols);
-        st_any(dst, d32, (int64_t)i * ldd + j, ld_any(src, s32, (int64_t)i * lds + j));
-    }
+template <typename TD, typename TS>
+__global__ void copy2d_kernel(int rows, int cols, TD* dst, int64_t ldd, const TS* src, int64_t lds) {
+    for (int i = blockIdx.y; i < rows; i += gridDim.y)
+        for (int j = blockIdx.x * TPB + threadIdx.x; j < cols; j += gridDim.x * TPB)
+            dst[(int64_t)i * ldd + j] = (TD)src[(int64_t)i * lds + j];
 }
 
-__global__ void copy2d_r32_kernel(int rows, int cols, double* dst, int64_t ldd, const void* src, bool s32,
-                                  int64_t lds) {
-    const int64_t n = (int64_t)rows * cols;
-    for (int64_t idx = blockIdx.x * (int64_t)TPB + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * TPB) {
-        const int i = (int)(idx / cols), j = (int)(idx - (int64_t)i * cols);
-        dst[(int64_t)i * ldd + j] = (double)(float)ld_any(src, s32, (int64_t)i * lds + j);
-    }
+template <typename TS>
+__global__ void copy2d_r32_kernel(int rows, int cols, double* dst, int64_t ldd, const TS* src, int64_t lds) {
+    for (int i = blockIdx.y; i < rows; i += gridDim.y)
+        for (int j = blockIdx.x * TPB + threadIdx.x; j < cols; j += gridDim.x * TPB)
+            dst[(int64_t)i * ldd + j] = (double)(float)src[(int64_t)i * lds + j];
+}
+
+__global__ void zero2d_kernel(int rows, int cols, double* dst, int64_t ldd) {
+    for (int i = blockIdx.y; i < rows; i += gridDim.y)
+        for (int j = blockIdx.x * TPB + threadIdx.x; j < cols; j += gridDim.x * TPB) dst[(int64_t)i * ldd + j] = 0.0;
 }
 
 // Dc[k][j] = (J[k+1][j] - J[k][j]) - mean_k(J[k+1][j] - J[k][j]), k < T-1; one thread per column.
@@ -122,14 +136,6 @@ __global__ void diff_center_kernel(const double* J, int64_t ldj, int T, int N, d
 __global__ void add_diag_kernel(double* A, int64_t lda, int n, double v) {
     const int i = blockIdx.x * TPB + threadIdx.x;
     if (i < n) A[(int64_t)i * lda + i] += v;
-}
-
-__global__ void zero2d_kernel(int rows, int cols, double* dst, int64_t ldd) {
-    const int64_t n = (int64_t)rows * cols;
-    for (int64_t idx = blockIdx.x * (int64_t)TPB + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * TPB) {
-        const int i = (int)(idx / cols), j = (int)(idx - (int64_t)i * cols);
-        dst[(int64_t)i * ldd + j] = 0.0;
-    }
 }
 
 __global__ void nonfinite_kernel(const double* v, int64_t n, int* flag) {
@@ -170,6 +176,48 @@ __global__ __launch_bounds__(256) void transpose_inplace_kernel(double* A, int64
 
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + TPB - 1) / TPB, 65536)); }
 
+dim3 grid2d(int rows, int cols) {
+    return dim3((unsigned)std::max(1, std::min((cols + TPB - 1) / TPB, 64)), (unsigned)std::max(1, std::min(rows, 65535)));
+}
+
+template <typename TD, typename TA, typename TB>
+hipError_t axpby3_c(int rows, int cols, TD* D, int64_t ldd, const TA* a, int64_t lda, const TB* b, int64_t ldb,
+                    double cb, const void* c, bool c32, int64_t ldc, double cc, hipStream_t s) {
+    if (c32)
+        hipLaunchKernelGGL((axpby3_kernel<TD, TA, TB, float>), grid2d(rows, cols), dim3(TPB), 0, s, rows, cols, D, ldd,
+                           a, lda, b, ldb, cb, static_cast<const float*>(c), ldc, cc);
+    else
+        hipLaunchKernelGGL((axpby3_kernel<TD, TA, TB, double>), grid2d(rows, cols), dim3(TPB), 0, s, rows, cols, D,
+                           ldd, a, lda, b, ldb, cb, static_cast<const double*>(c), ldc, cc);
+    return hipGetLastError();
+}
+
+template <typename TD, typename TA>
+hipError_t axpby3_b(int rows, int cols, TD* D, int64_t ldd, const TA* a, int64_t lda, const void* b, bool b32,
+                    int64_t ldb, double cb, const void* c, bool c32, int64_t ldc, double cc, hipStream_t s) {
+    if (b32) return axpby3_c(rows, cols, D, ldd, a, lda, static_cast<const float*>(b), ldb, cb, c, c32, ldc, cc, s);
+    return axpby3_c(rows, cols, D, ldd, a, lda, static_cast<const double*>(b), ldb, cb, c, c32, ldc, cc, s);
+}
+
+template <typename TD>
+hipError_t axpby3_a(int rows, int cols, TD* D, int64_t ldd, const void* a, bool a32, int64_t lda, const void* b,
+                    bool b32, int64_t ldb, double cb, const void* c, bool c32, int64_t ldc, double cc, hipStream_t s) {
+    if (a32)
+        return axpby3_b(rows, cols, D, ldd, static_cast<const float*>(a), lda, b, b32, ldb, cb, c, c32, ldc, cc, s);
+    return axpby3_b(rows, cols, D, ldd, static_cast<const double*>(a), lda, b, b32, ldb, cb, c, c32, ldc, cc, s);
+}
+
+template <typename TD>
+hipError_t copy2d_t(int rows, int cols, TD* dst, int64_t ldd, const void* src, bool s32, int64_t lds, hipStream_t s) {
+    if (s32)
+        hipLaunchKernelGGL((copy2d_kernel<TD, float>), grid2d(rows, cols), dim3(TPB), 0, s, rows, cols, dst, ldd,
+                           static_cast<const float*>(src), lds);
+    else
+        hipLaunchKernelGGL((copy2d_kernel<TD, double>), grid2d(rows, cols), dim3(TPB), 0, s, rows, cols, dst, ldd,
+                           static_cast<const double*>(src), lds);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t resid(const double* X, int64_t ldx, const double* x, const double* y, double* e, int m, int N,
@@ -185,7 +233,7 @@ hipError_t trmv_lower(const double* L, int64_t ldl, const double* e, double* w, 
 
 hipError_t gemv_t_add(const double* C, int64_t ldc, const double* w, const double* x_in, double* x_out,
                       double* x_copy, int m, int N, hipStream_t s) {
-    hipLaunchKernelGGL(gemv_t_add_kernel, dim3((N + TPB - 1) / TPB), dim3(TPB), 0, s, C, ldc, w, x_in, x_out,
+    hipLaunchKernelGGL(gemv_t_add_kernel, dim3((N + GT_COLS - 1) / GT_COLS), dim3(TPB), 0, s, C, ldc, w, x_in, x_out,
                        x_copy, m, N);
     return hipGetLastError();
 }
@@ -199,22 +247,27 @@ hipError_t gemv_smooth(const double* A, int64_t lda, const double* x, const doub
 hipError_t axpby3(int rows, int cols, void* D, bool d32, int64_t ldd, const void* a, bool a32, int64_t lda,
                   const void* b, bool b32, int64_t ldb, double cb, const void* c, bool c32, int64_t ldc,
                   double cc, hipStream_t s) {
-    hipLaunchKernelGGL(axpby3_kernel, dim3(grid_for((int64_t)rows * cols)), dim3(TPB), 0, s, rows, cols, D, d32,
-                       ldd, a, a32, lda, b, b32, ldb, cb, c, c32, ldc, cc);
-    return hipGetLastError();
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if (d32) return axpby3_a(rows, cols, static_cast<float*>(D), ldd, a, a32, lda, b, b32, ldb, cb, c, c32, ldc, cc, s);
+    return axpby3_a(rows, cols, static_cast<double*>(D), ldd, a, a32, lda, b, b32, ldb, cb, c, c32, ldc, cc, s);
 }
 
 hipError_t copy2d(int rows, int cols, void* dst, bool d32, int64_t ldd, const void* src, bool s32, int64_t lds,
                   hipStream_t s) {
-    hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for((int64_t)rows * cols)), dim3(TPB), 0, s, rows, cols, dst, d32,
-                       ldd, src, s32, lds);
-    return hipGetLastError();
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if (d32) return copy2d_t(rows, cols, static_cast<float*>(dst), ldd, src, s32, lds, s);
+    return copy2d_t(rows, cols, static_cast<double*>(dst), ldd, src, s32, lds, s);
 }
 
 hipError_t copy2d_r32(int rows, int cols, double* dst, int64_t ldd, const void* src, bool s32, int64_t lds,
                       hipStream_t s) {
-    hipLaunchKernelGGL(copy2d_r32_kernel, dim3(grid_for((int64_t)rows * cols)), dim3(TPB), 0, s, rows, cols, dst, ldd,
-                       src, s32, lds);
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if (s32)
+        hipLaunchKernelGGL((copy2d_r32_kernel<float>), grid2d(rows, cols), dim3(TPB), 0, s, rows, cols, dst, ldd,
+                           static_cast<const float*>(src), lds);
+    else
+        hipLaunchKernelGGL((copy2d_r32_kernel<double>), grid2d(rows, cols), dim3(TPB), 0, s, rows, cols, dst, ldd,
+                           static_cast<const double*>(src), lds);
     return hipGetLastError();
 }
 
@@ -229,7 +282,8 @@ hipError_t add_diag(double* A, int64_t lda, int n, double v, hipStream_t s) {
 }
 
 hipError_t zero2d(int rows, int cols, double* dst, int64_t ldd, hipStream_t s) {
-    hipLaunchKernelGGL(zero2d_kernel, dim3(grid_for((int64_t)rows * cols)), dim3(TPB), 0, s, rows, cols, dst, ldd);
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero2d_kernel, grid2d(rows, cols), dim3(TPB), 0, s, rows, cols, dst, ldd);
     return hipGetLastError();
 }
 
