@@ -33,6 +33,18 @@ int kfd_gemm(int dtype, int M, int N, int K, int flags, const void* A, int64_t l
              int64_t ldc, int ksplit, void* stream);
 
 /*
+ * kfd_gemm with tail splitting (flags and other arguments as for kfd_gemm,
+ * ksplit = 1): the first `full` tiles of the problem's tile order are
+ * computed whole and the remaining ones split `k` ways along K (2 <= k <= 8),
+ * each split tile reduced by its own workgroup. The library uses this for the
+ * smoother's largest products so that the last wave of workgroups is not left
+ * mostly idle. Returns 0, 1 on bad arguments, 4 on a HIP error.
+ */
+int kfd_gemm_tail(int dtype, int M, int N, int K, int flags, const void* A, int64_t lda, const void* B,
+                  int64_t ldb, double alpha, double beta, const double* Cin, int64_t ldcin, double* C,
+                  int64_t ldc, int full, int k, void* stream);
+
+/*
  * Cholesky factor and its inverse of the SPD matrix in the lower triangle of
  * W (n x n, ld ldw): on return the lower triangle of W holds L (the strict
  * upper triangle is not part of the result) and Z (n x n, ld ldz) holds

@@ -30,6 +30,32 @@ int kfd_gemm(int dtype, int M, int N, int K, int flags, const void* A, int64_t l
     return e == hipSuccess ? 0 : 4;
 }
 
+int kfd_gemm_tail(int dtype, int M, int N, int K, int flags, const void* A, int64_t lda, const void* B,
+                  int64_t ldb, double alpha, double beta, const double* Cin, int64_t ldcin, double* C, int64_t ldc,
+                  int full, int k, void* stream) {
+    if (M <= 0 || N <= 0 || K < 0 || !A || !B || !C || (dtype != 0 && dtype != 1) || (flags & ~127) || k < 2 ||
+        k > 8 || full < 0)
+        return 1;
+    if ((flags & G_LOWER) && M != N) return 1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GemmProblem g;
+    g.M = M; g.N = N; g.K = K; g.flags = flags;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb;
+    g.alpha = alpha; g.beta = beta; g.Cin = Cin; g.ldcin = ldcin;
+    g.C = C; g.ldc = ldc;
+    const int tiles = gemm_tiles(g);
+    if (full > tiles) return 1;
+    TailSplit ts;
+    ts.full = full;
+    ts.k = k;
+    void* ws = nullptr;
+    if (hipMalloc(&ws, (size_t)(tiles - full) * k * kTileElems * (dtype == 0 ? 8 : 4) + 256) != hipSuccess) return 4;
+    hipError_t e = gemm_launch_tail(dtype == 0 ? Dt::F64 : Dt::F32, g, ts, ws, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(ws);
+    return e == hipSuccess ? 0 : 4;
+}
+
 int kfd_chol_inv(int n, double* W, int64_t ldw, double* Z, int64_t ldz, int* pivot_row, void* stream) {
     if (n <= 0 || !W || !Z || ldw < n || ldz < n) return 1;
     hipStream_t s = static_cast<hipStream_t>(stream);

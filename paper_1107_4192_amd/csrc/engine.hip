@@ -70,6 +70,10 @@ struct kf_plan {
     double* Ps[2] = {nullptr, nullptr};
     double *Dm = nullptr, *Mm = nullptr;    // D = P_{t+1|T} - P_{t+1|t} and M = A_t D (float64 path)
     float *D32 = nullptr, *M32 = nullptr;   // the same in float32 (mixed path)
+    // tail splitting of the two N x N x N products of the back-recursion (M = A_t D, whole;
+    // P_t + M A_t^T, lower tiles), chosen once per plan
+    TailSplit ts_m, ts_low;
+    void* tail_ws = nullptr;
     hipStream_t s2 = nullptr;
     hipEvent_t ev_start = nullptr, ev_gain[2] = {nullptr, nullptr}, ev_chain[2] = {nullptr, nullptr};
     // status
@@ -170,6 +174,30 @@ size_t store_bytes(int64_t N, int64_t ldN, int64_t T, bool s32, int stride) {
     return (size_t)slots_needed(T, stride) * (size_t)N * ldN * (s32 && stride == 1 ? 4 : 8);
 }
 
+// Tail splits of the back-recursion's M = A_t D (whole) and P_t + M A_t^T (lower) products.
+constexpr int kTailUnits = 2048;
+void tail_splits(int64_t N, TailSplit& ts_m, TailSplit& ts_low) {
+    GemmProblem g;
+    g.M = g.N = g.K = (int)N;
+    const int slots = gemm_slots(), kiters = (int)((N + 15) / 16);
+    ts_m = choose_tail_split(gemm_tiles(g), kiters, slots, kTailUnits);
+    g.flags = G_LOWER;
+    ts_low = choose_tail_split(gemm_tiles(g), kiters, slots, kTailUnits);
+}
+
+size_t tail_bytes(int64_t N, bool mix) {
+    TailSplit a, b;
+    tail_splits(N, a, b);
+    GemmProblem g;
+    g.M = g.N = g.K = (int)N;
+    const int full = gemm_tiles(g);
+    g.flags = G_LOWER;
+    const int low = gemm_tiles(g);
+    const size_t units = std::max<size_t>(a.k > 1 ? (size_t)(full - a.full) * a.k : 0,
+                                          b.k > 1 ? (size_t)(low - b.full) * b.k : 0);
+    return units * kTileElems * (mix ? 4 : 8);
+}
+
 size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int gb) {
     const int64_t ldN = round_up(N, 16), ldm = round_up(m, 16);
     const size_t NN = (size_t)N * ldN;
@@ -184,6 +212,7 @@ size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int
     if (s32 || stride > 1) b += 8 * 2 * NN;
     if (mix) b += 4 * NN;
     if (stride > 1) b += (size_t)stride * NN * (s32 ? 4 : 8);
+    b += tail_bytes(N, mix);
     return b;
 }
 
@@ -364,7 +393,8 @@ kf_status sync_and_check(kf_plan* p, const char* phase) {
 }
 
 // Launch a group of the smoother's N x N x N products (named instantiation), timed when profiling.
-kf_status big_group(kf_plan* p, Dt dt, GemmProblem* g, int count, double flops, hipStream_t st) {
+kf_status big_group(kf_plan* p, Dt dt, GemmProblem* g, int count, double flops, hipStream_t st,
+                    const TailSplit* ts = nullptr) {
     for (int u = 0; u < count; ++u) g[u].flags |= mixed(p) ? G_NXN_MIXED : G_NXN;
     if (p->prof) {
         while (p->ev.size() < p->ev_used + 2) {
@@ -374,7 +404,8 @@ kf_status big_group(kf_plan* p, Dt dt, GemmProblem* g, int count, double flops, 
         }
         HIPCK(hipEventRecord(p->ev[p->ev_used], st));
     }
-    HIPCK(gemm_launch(dt, g, count, st));
+    if (ts && ts->k > 1 && p->tail_ws && count == 1) HIPCK(gemm_launch_tail(dt, g[0], *ts, p->tail_ws, st));
+    else HIPCK(gemm_launch(dt, g, count, st));
     if (p->prof) {
         HIPCK(hipEventRecord(p->ev[p->ev_used + 1], st));
         p->ev_flops.push_back(flops);
@@ -383,8 +414,8 @@ kf_status big_group(kf_plan* p, Dt dt, GemmProblem* g, int count, double flops, 
     return KF_OK;
 }
 
-kf_status big_gemm(kf_plan* p, Dt dt, GemmProblem g, double flops, hipStream_t st) {
-    return big_group(p, dt, &g, 1, flops, st);
+kf_status big_gemm(kf_plan* p, Dt dt, GemmProblem g, double flops, hipStream_t st, const TailSplit* ts = nullptr) {
+    return big_group(p, dt, &g, 1, flops, st, ts);
 }
 
 // After the stream has been synchronised: fold the recorded event pairs into the totals.
@@ -510,6 +541,10 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
         }
     }
     ALLOC(p->Ps[0], NN); ALLOC(p->Ps[1], NN);
+    tail_splits(N, p->ts_m, p->ts_low);
+    if (const size_t tb = tail_bytes(N, mix)) {
+        if ((st = alloc_bytes(p, &p->tail_ws, tb)) != KF_OK) return fail(st);
+    }
     if (!mix) { ALLOC(p->Dm, NN); ALLOC(p->Mm, NN); }
     if (mix) {
         ALLOC(p->Cm32, mN);
@@ -746,13 +781,13 @@ kf_status chain_step(kf_plan* p, int set, int b, int64_t t, const void* Pt, cons
         g.M = N; g.N = N; g.K = N;
         g.A = p->A32[set][b]; g.lda = ld; g.B = p->D32; g.ldb = ld; g.flags = G_TB;   // D symmetric
         g.C32 = p->M32; g.ldc32 = ld;
-        TRY(big_gemm(p, Dt::F32, g, 2.0 * N * N * N, s));
+        TRY(big_gemm(p, Dt::F32, g, 2.0 * N * N * N, s, &p->ts_m));
         GemmProblem h;
         h.M = N; h.N = N; h.K = N;
         h.A = p->M32; h.lda = ld; h.B = p->A32[set][b]; h.ldb = ld; h.flags = G_TB | G_LOWER | G_MIRROR;
         h.Cin = Pt64; h.ldcin = ld; h.beta = 1.0;
         h.C = Ps_out; h.ldc = ld; h.diag = Pdiag;
-        TRY(big_gemm(p, Dt::F32, h, (double)N * N * N, s));
+        TRY(big_gemm(p, Dt::F32, h, (double)N * N * N, s, &p->ts_low));
     } else {
         // D = P_{t+1|T} - P_t - Q;  M = A_t D;  P_{t|T} = P_t + M A_t^T   (eqn13)
         HIPCK(axpby3(N, N, p->Dm, false, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
@@ -761,13 +796,13 @@ kf_status chain_step(kf_plan* p, int set, int b, int64_t t, const void* Pt, cons
         g.A = A; g.lda = ld;
         g.B = p->Dm; g.ldb = ld; g.flags = G_TB;   // D symmetric: read row-contiguous
         g.C = p->Mm; g.ldc = ld;
-        TRY(big_gemm(p, Dt::F64, g, 2.0 * N * N * N, s));
+        TRY(big_gemm(p, Dt::F64, g, 2.0 * N * N * N, s, &p->ts_m));
         GemmProblem h;
         h.M = N; h.N = N; h.K = N;
         h.A = p->Mm; h.lda = ld; h.B = A; h.ldb = ld; h.flags = G_TB | G_LOWER | G_MIRROR;
         h.Cin = Pt64; h.ldcin = ld; h.beta = 1.0;
         h.C = Ps_out; h.ldc = ld; h.diag = Pdiag;
-        TRY(big_gemm(p, Dt::F64, h, (double)N * N * N, s));
+        TRY(big_gemm(p, Dt::F64, h, (double)N * N * N, s, &p->ts_low));
     }
     return KF_OK;
 }

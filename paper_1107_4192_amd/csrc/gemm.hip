@@ -17,12 +17,42 @@
 #include "kf_internal.h"
 
 #include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <functional>
+#include <queue>
+#include <vector>
 
 namespace kfmeg {
 
 namespace {
 
 constexpr int BM = 128, BN = 128, BK = 16, NT = 256;
+
+// Device-side problem descriptor: what the kernels read of a GemmProblem, packed into 128
+// bytes so that a group of kMaxGroup problems stays a small kernel argument (the whole group
+// is passed by value; launches with larger argument blocks ran measurably slower).
+struct GemmDesc {
+    const void *A, *B, *Cin, *Cin2;
+    double* C;
+    float* C32;          // shares C's leading dimension
+    double* diag;
+    void* partial;
+    double alpha, beta;  // Cin2 enters with coefficient 1
+    int M, N, K, flags;
+    int lda, ldb, ldcin, ldcin2, ldc;
+    int ksplit, tile_off, tile_begin;
+    __device__ __forceinline__ int tiles_m() const { return (M + 127) / 128; }
+    __device__ __forceinline__ int tiles_n() const { return (N + 127) / 128; }
+};
+static_assert(sizeof(GemmDesc) == 128, "GemmDesc layout");
+
+struct GemmGroup {
+    GemmDesc p[kMaxGroup];
+    int count = 0;
+    int total_tiles = 0;
+    int remap = 1;     // group equal-cost tiles per XCD (off when K ranges vary per tile)
+};
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -72,7 +102,7 @@ __device__ __forceinline__ void load8(T (&r)[8], const T* p, int nvalid, bool ve
 
 // Operand A tile: rows i0..i0+BM, k in [k0, k0+BK) clipped to [.., khi); into regs.
 template <typename T>
-__device__ __forceinline__ void fetch_a(T (&r)[8], const GemmProblem& P, int i0, int k0, int khi, int tid) {
+__device__ __forceinline__ void fetch_a(T (&r)[8], const GemmDesc& P, int i0, int k0, int khi, int tid) {
     const T* A = static_cast<const T*>(P.A);
     const bool vec = !(P.flags & G_SCALAR);
     if (!(P.flags & G_TA)) {            // A[i*lda + k]: row r, 8 consecutive k
@@ -97,7 +127,7 @@ __device__ __forceinline__ void fetch_a(T (&r)[8], const GemmProblem& P, int i0,
 }
 
 template <typename T>
-__device__ __forceinline__ void fetch_b_one(T (&r)[8], const T* B, int64_t ldb, bool tb, const GemmProblem& P,
+__device__ __forceinline__ void fetch_b_one(T (&r)[8], const T* B, int64_t ldb, bool tb, const GemmDesc& P,
                                             int j0, int k0, int khi, int tid, bool vec) {
     if (!tb) {                          // B[k*ldb + j]: k row, 8 consecutive j
         const int kr = tid >> 4, js = (tid & 15) * 8;
@@ -121,7 +151,7 @@ __device__ __forceinline__ void fetch_b_one(T (&r)[8], const T* B, int64_t ldb, 
 }
 
 template <typename T>
-__device__ __forceinline__ void fetch_b(T (&r)[8], const GemmProblem& P, int j0, int k0, int khi, int tid) {
+__device__ __forceinline__ void fetch_b(T (&r)[8], const GemmDesc& P, int j0, int k0, int khi, int tid) {
     const bool tb = P.flags & G_TB;
     const bool vec = !(P.flags & G_SCALAR);
     fetch_b_one<T>(r, static_cast<const T*>(P.B), P.ldb, tb, P, j0, k0, khi, tid, vec);
@@ -154,6 +184,28 @@ __device__ __forceinline__ void tri_decode(int t, int& bm, int& bn) {
     bn = t - r * (r + 1) / 2;
 }
 
+// Tile (bm, bn) of linear index `local` in the problem's tile order.
+__device__ __forceinline__ void decode_tile(const GemmDesc& P, int local, int& bm, int& bn) {
+    if (P.flags & G_LOWER) tri_decode(local, bm, bn);
+    else if (P.flags & G_ALOWER) {            // longest tiles (largest K range) first
+        bm = P.tiles_m() - 1 - local / P.tiles_n(); bn = local % P.tiles_n();
+    } else if (P.flags & G_BLOWER) {
+        bn = local / P.tiles_m(); bm = local % P.tiles_m();
+    } else if (P.flags & G_BUPPER) {
+        bn = P.tiles_n() - 1 - local / P.tiles_m(); bm = local % P.tiles_m();
+    } else {
+        // Groups of 8 tile rows, column-major inside a group: the 64 workgroups an XCD runs
+        // at once cover about an 8 x 8 block of tiles and share their operand panels in L2.
+        constexpr int GM = 8;
+        const int per_group = GM * P.tiles_n();
+        const int group = local / per_group, first = group * GM;
+        const int gsize = min(P.tiles_m() - first, GM);
+        const int in = local - group * per_group;
+        bm = first + in % gsize;
+        bn = in / gsize;
+    }
+}
+
 // c[b][r] = src(ii, jj) as float64 for the 16 elements of one strip (element 0 where !ok).
 __device__ __forceinline__ void gather_strip(double (&c)[4][4], const void* src, bool f32, int64_t ld,
                                              const int (&ii)[4][4], const int (&jj)[4][4], const bool (&ok)[4][4]) {
@@ -172,16 +224,28 @@ __device__ __forceinline__ void gather_strip(double (&c)[4][4], const void* src,
     }
 }
 
-// Result of one tile: raw partial sums (split-K), or C = alpha acc + beta Cin + gamma Cin2
+// Result of one tile: raw partial sums (split-K), or C = alpha acc + beta Cin + Cin2
 // with the lower / mirror / diagonal / float32 options. Lane (lk, lr) of wave (wm, wn) holds
 // acc[a][b][r] = C(i0 + wm + 16a + row(lk, r), j0 + wn + 16b + lr).
+// `slot` is the tile's index within a G_TILEPART range; `final` forces the result path (the
+// tile-wise reduction calls it with the summed partials).
 template <typename T>
-__device__ __forceinline__ void epilogue(const GemmProblem& P, const typename Acc<T>::V (&acc)[4][4], int i0,
-                                         int j0, int split, int tid) {
+__device__ __forceinline__ void epilogue(const GemmDesc& P, const typename Acc<T>::V (&acc)[4][4], int i0,
+                                         int j0, int split, int slot, int tid, bool final = false) {
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
     const int lr = lane & 15, lk = lane >> 4;
-    if (P.ksplit > 1) {
+    if (P.ksplit > 1 && !final && (P.flags & G_TILEPART)) {
+        T* part = static_cast<T*>(P.partial) + ((int64_t)slot * P.ksplit + split) * kTileElems;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) part[((a * 4 + b) * 4 + r) * NT + tid] = acc[a][b][r];
+        return;
+    }
+    if (P.ksplit > 1 && !final) {
         T* part = static_cast<T*>(P.partial) + (int64_t)split * P.M * P.N;
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -222,13 +286,13 @@ __device__ __forceinline__ void epilogue(const GemmProblem& P, const typename Ac
                 const int i = ii[b][r], j = jj[b][r];
                 double v = P.alpha * (double)acc[a][b][r];
                 if (P.Cin) v += P.beta * c1[b][r];
-                if (P.Cin2) v += P.gamma * c2[b][r];
+                if (P.Cin2) v += c2[b][r];
                 if (P.C) P.C[(int64_t)i * P.ldc + j] = v;
-                if (P.C32) P.C32[(int64_t)i * P.ldc32 + j] = (float)v;
+                if (P.C32) P.C32[(int64_t)i * P.ldc + j] = (float)v;
                 if (P.diag && i == j) P.diag[i] = v;
                 if (mirror && i > j) {
                     if (P.C) P.C[(int64_t)j * P.ldc + i] = v;
-                    if (P.C32) P.C32[(int64_t)j * P.ldc32 + i] = (float)v;
+                    if (P.C32) P.C32[(int64_t)j * P.ldc + i] = (float)v;
                 }
             }
     }
@@ -247,14 +311,15 @@ __global__ __launch_bounds__(NT) void gemm_generic_kernel(GemmGroup G) {
 #pragma unroll
     for (int u = 1; u < kMaxGroup; ++u)
         if (u < G.count && bid >= G.p[u].tile_begin) q = u;
-    const GemmProblem& P = G.p[q];
+    const GemmDesc& P = G.p[q];
 
     int local = bid - P.tile_begin;
     const int split = local % P.ksplit;
     local /= P.ksplit;
+    const int slot = local;
+    local += P.tile_off;
     int bm, bn;
-    if (P.flags & G_LOWER) tri_decode(local, bm, bn);
-    else { bm = local / P.tiles_n; bn = local - bm * P.tiles_n; }
+    decode_tile(P, local, bm, bn);
     const int i0 = bm * BM, j0 = bn * BN;
 
     // K range of this tile (triangular operands hold explicit zeros, so trimming is exact).
@@ -321,12 +386,12 @@ __global__ __launch_bounds__(NT) void gemm_generic_kernel(GemmGroup G) {
         }
     }
 
-    epilogue<T>(P, acc, i0, j0, split, tid);
+    epilogue<T>(P, acc, i0, j0, split, slot, tid);
 }
 
 // Split-K reduction in fixed split order (deterministic), then the epilogue.
 template <typename T>
-__global__ void gemm_reduce_kernel(GemmProblem P) {
+__global__ void gemm_reduce_kernel(GemmDesc P) {
     const int64_t n = (int64_t)P.M * P.N;
     const T* part = static_cast<const T*>(P.partial);
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
@@ -337,13 +402,13 @@ __global__ void gemm_reduce_kernel(GemmProblem P) {
         for (int sp = 0; sp < P.ksplit; ++sp) s += (double)part[sp * n + idx];
         double v = P.alpha * s;
         if (P.Cin) v += P.beta * load_any(P.Cin, P.flags & G_CIN32, (int64_t)i * P.ldcin + j);
-        if (P.Cin2) v += P.gamma * load_any(P.Cin2, P.flags & G_CIN2_32, (int64_t)i * P.ldcin2 + j);
+        if (P.Cin2) v += load_any(P.Cin2, P.flags & G_CIN2_32, (int64_t)i * P.ldcin2 + j);
         if (P.C) P.C[(int64_t)i * P.ldc + j] = v;
-        if (P.C32) P.C32[(int64_t)i * P.ldc32 + j] = (float)v;
+        if (P.C32) P.C32[(int64_t)i * P.ldc + j] = (float)v;
         if (P.diag && i == j) P.diag[i] = v;
         if ((P.flags & G_MIRROR) && i > j) {
             if (P.C) P.C[(int64_t)j * P.ldc + i] = v;
-            if (P.C32) P.C32[(int64_t)j * P.ldc32 + i] = (float)v;
+            if (P.C32) P.C32[(int64_t)j * P.ldc + i] = (float)v;
         }
     }
 }
@@ -432,7 +497,7 @@ struct Operand {
 };
 
 template <typename T, bool TA, bool TB>
-__device__ __forceinline__ void fast_tile(const GemmProblem& P, int bm, int bn, int split, T* As, T* Bs) {
+__device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int split, int slot, T* As, T* Bs) {
     using AV = typename Acc<T>::V;
     const int tid = threadIdx.x;
     const int i0 = bm * BM, j0 = bn * BN;
@@ -495,7 +560,7 @@ __device__ __forceinline__ void fast_tile(const GemmProblem& P, int bm, int bn, 
             __syncthreads();
         }
     }
-    epilogue<T>(P, acc, i0, j0, split, tid);
+    epilogue<T>(P, acc, i0, j0, split, slot, tid);
 }
 
 // V selects a separately named instantiation: 1 for the smoother's N x N x N
@@ -506,41 +571,54 @@ template <typename T, int V, int MASK>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmGroup G) {
     __shared__ T As[2 * BK * BM];
     __shared__ T Bs[2 * BK * BN];
-    // Tiles of equal cost are grouped per XCD; tiles whose K range varies (triangular
-    // operands) keep the round-robin spread so that every XCD gets a fair share.
-    const int bid = G.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     int q = 0;
 #pragma unroll
     for (int u = 1; u < kMaxGroup; ++u)
-        if (u < G.count && bid >= G.p[u].tile_begin) q = u;
-    const GemmProblem& P = G.p[q];
-    int local = bid - P.tile_begin;
+        if (u < G.count && (int)blockIdx.x >= G.p[u].tile_begin) q = u;
+    const GemmDesc& P = G.p[q];
+    int local = (int)blockIdx.x - P.tile_begin;
+    // Tiles of equal cost are grouped per XCD (each problem's range on its own, so that the
+    // problems of a group keep their dispatch order); tiles whose K range varies (triangular
+    // operands) keep the round-robin spread so that every XCD gets a fair share.
+    if (G.remap) {
+        const int end = q + 1 < G.count ? G.p[q + 1].tile_begin : (int)gridDim.x;
+        local = xcd_remap(local, end - P.tile_begin);
+    }
     const int split = local % P.ksplit;
     local /= P.ksplit;
+    const int slot = local;
+    local += P.tile_off;
     int bm, bn;
-    if (P.flags & G_LOWER) tri_decode(local, bm, bn);
-    else if (P.flags & G_ALOWER) {            // longest tiles (largest K range) first
-        bm = P.tiles_m - 1 - local / P.tiles_n; bn = local % P.tiles_n;
-    } else if (P.flags & G_BLOWER) {
-        bn = local / P.tiles_m; bm = local % P.tiles_m;
-    } else if (P.flags & G_BUPPER) {
-        bn = P.tiles_n - 1 - local / P.tiles_m; bm = local % P.tiles_m;
-    } else {
-        // Groups of 8 tile rows, column-major inside a group: the 64 workgroups an XCD runs
-        // at once cover about an 8 x 8 block of tiles and share their operand panels in L2.
-        constexpr int GM = 8;
-        const int per_group = GM * P.tiles_n;
-        const int group = local / per_group, first = group * GM;
-        const int gsize = min(P.tiles_m - first, GM);
-        const int in = local - group * per_group;
-        bm = first + in % gsize;
-        bn = in / gsize;
-    }
+    decode_tile(P, local, bm, bn);
     const int lay = (P.flags & G_TA ? 1 : 0) | (P.flags & G_TB ? 2 : 0);
-    if ((MASK & 1) && lay == 0) fast_tile<T, false, false>(P, bm, bn, split, As, Bs);
-    else if ((MASK & 2) && lay == 1) fast_tile<T, true, false>(P, bm, bn, split, As, Bs);
-    else if ((MASK & 4) && lay == 2) fast_tile<T, false, true>(P, bm, bn, split, As, Bs);
-    else if ((MASK & 8) && lay == 3) fast_tile<T, true, true>(P, bm, bn, split, As, Bs);
+    if ((MASK & 1) && lay == 0) fast_tile<T, false, false>(P, bm, bn, split, slot, As, Bs);
+    else if ((MASK & 2) && lay == 1) fast_tile<T, true, false>(P, bm, bn, split, slot, As, Bs);
+    else if ((MASK & 4) && lay == 2) fast_tile<T, false, true>(P, bm, bn, split, slot, As, Bs);
+    else if ((MASK & 8) && lay == 3) fast_tile<T, true, true>(P, bm, bn, split, slot, As, Bs);
+}
+
+// Tile-wise reduction of a G_TILEPART range: one workgroup per tile sums the k slices in a
+// fixed order (deterministic) and applies the epilogue.
+template <typename T>
+__global__ __launch_bounds__(NT) void gemm_tile_reduce_kernel(GemmDesc P) {
+    using AV = typename Acc<T>::V;
+    const int slot = blockIdx.x, tid = threadIdx.x;
+    int bm, bn;
+    decode_tile(P, P.tile_off + slot, bm, bn);
+    const T* part = static_cast<const T*>(P.partial) + (int64_t)slot * P.ksplit * kTileElems;
+    AV acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int idx = ((a * 4 + b) * 4 + r) * NT + tid;
+                T v = part[idx];
+                for (int sp = 1; sp < P.ksplit; ++sp) v += part[(int64_t)sp * kTileElems + idx];
+                acc[a][b][r] = v;
+            }
+    epilogue<T>(P, acc, bm * BM, bn * BN, 0, slot, tid, true);
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -576,24 +654,41 @@ hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s) {
     const int vec_elems = 16 / esz;
     bool fast = true;
     int layouts[kMaxGroup] = {};
+    int tile_cnt[kMaxGroup] = {};
+    auto fits = [](int64_t v) { return v >= 0 && v <= INT32_MAX; };
     for (int u = 0; u < count; ++u) {
-        GemmProblem p = probs[u];
+        const GemmProblem& p = probs[u];
         if (p.M <= 0 || p.N <= 0) continue;
-        if (p.ksplit < 1) p.ksplit = 1;
-        p.tiles_m = (p.M + BM - 1) / BM;
-        p.tiles_n = (p.N + BN - 1) / BN;
+        const int ks = p.ksplit < 1 ? 1 : p.ksplit;
+        const int tm = (p.M + BM - 1) / BM, tn = (p.N + BN - 1) / BN;
         if ((p.flags & G_LOWER) && p.M != p.N) return hipErrorInvalidValue;
+        if (p.Cin2 && p.gamma != 1.0) return hipErrorInvalidValue;
+        if (p.C && p.C32 && p.ldc32 != p.ldc) return hipErrorInvalidValue;
+        if (!fits(p.lda) || !fits(p.ldb) || !fits(p.ldcin) || !fits(p.ldcin2) || !fits(p.ldc) || !fits(p.ldc32))
+            return hipErrorInvalidValue;
         const bool ta = p.flags & G_TA, tb = p.flags & G_TB;
+        int flags = p.flags;
         bool vec = aligned16(p.A) && aligned16(p.B) && p.lda % vec_elems == 0 && p.ldb % vec_elems == 0;
-        if (!vec) p.flags |= G_SCALAR;
-        fast = fast && p.K > 0 && fast_ok(p.A, p.lda, ta ? p.M : p.K) &&
-               fast_ok(p.B, p.ldb, tb ? p.K : p.N);
-        p.tile_begin = total;
-        const int tiles = (p.flags & G_LOWER) ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
-        total += tiles * p.ksplit;
+        if (!vec) flags |= G_SCALAR;
+        const int all = (p.flags & G_LOWER) ? tm * (tm + 1) / 2 : tm * tn;
+        if (p.tile_off < 0 || p.tile_off > all) return hipErrorInvalidValue;
+        const int tiles = p.tile_cnt < 0 ? all - p.tile_off : std::min(p.tile_cnt, all - p.tile_off);
+        if ((p.flags & G_TILEPART) && (ks < 2 || !p.partial)) return hipErrorInvalidValue;
+        if (tiles == 0) continue;
         if (G.count >= kMaxGroup) return hipErrorInvalidValue;
+        fast = fast && p.K > 0 && fast_ok(p.A, p.lda, ta ? p.M : p.K) && fast_ok(p.B, p.ldb, tb ? p.K : p.N);
+        GemmDesc d;
+        d.A = p.A; d.B = p.B; d.Cin = p.Cin; d.Cin2 = p.Cin2;
+        d.C = p.C; d.C32 = p.C32; d.diag = p.diag; d.partial = p.partial;
+        d.alpha = p.alpha; d.beta = p.beta;
+        d.M = p.M; d.N = p.N; d.K = p.K; d.flags = flags;
+        d.lda = (int)p.lda; d.ldb = (int)p.ldb; d.ldcin = (int)p.ldcin; d.ldcin2 = (int)p.ldcin2;
+        d.ldc = (int)(p.C ? p.ldc : p.ldc32);
+        d.ksplit = ks; d.tile_off = p.tile_off; d.tile_begin = total;
+        total += tiles * ks;
         layouts[G.count] = (ta ? 1 : 0) | (tb ? 2 : 0);
-        G.p[G.count++] = p;
+        tile_cnt[G.count] = tiles;
+        G.p[G.count++] = d;
     }
     if (G.count == 0) return hipSuccess;
     G.total_tiles = total;
@@ -618,8 +713,14 @@ hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s) {
     }
     if (e != hipSuccess) return e;
     for (int u = 0; u < G.count; ++u) {
-        const GemmProblem& p = G.p[u];
+        const GemmDesc& p = G.p[u];
         if (p.ksplit <= 1) continue;
+        if (p.flags & G_TILEPART) {
+            if (dt == Dt::F64) hipLaunchKernelGGL(gemm_tile_reduce_kernel<double>, dim3(tile_cnt[u]), dim3(NT), 0, s, p);
+            else hipLaunchKernelGGL(gemm_tile_reduce_kernel<float>, dim3(tile_cnt[u]), dim3(NT), 0, s, p);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            continue;
+        }
         const int64_t n = (int64_t)p.M * p.N;
         const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
         if (dt == Dt::F64) hipLaunchKernelGGL(gemm_reduce_kernel<double>, dim3(blocks), dim3(256), 0, s, p);
@@ -628,6 +729,79 @@ hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+int gemm_tiles(const GemmProblem& p) {
+    const int tm = (p.M + BM - 1) / BM, tn = (p.N + BN - 1) / BN;
+    return (p.flags & G_LOWER) ? tm * (tm + 1) / 2 : tm * tn;
+}
+
+int gemm_slots() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    return 2 * cus;   // the fast path runs two workgroups per compute unit
+}
+
+namespace {
+
+// Makespan, in units of one whole tile's time, of `full` whole tiles followed by
+// (tiles - full) * k pieces of 1/k each, greedily placed on `slots` equal workers in
+// dispatch order (how the hardware hands out workgroups).
+double makespan(int tiles, int full, int k, int slots) {
+    std::vector<double> busy(slots, 0.0);
+    std::priority_queue<double, std::vector<double>, std::greater<double>> q(std::greater<double>(), busy);
+    double mk = 0.0;
+    auto place = [&](double d) {
+        const double t = q.top() + d;
+        q.pop();
+        q.push(t);
+        mk = std::max(mk, t);
+    };
+    for (int u = 0; u < full; ++u) place(1.0);
+    for (int u = 0; u < (tiles - full) * k; ++u) place(1.0 / k);
+    return mk;
+}
+
+}  // namespace
+
+TailSplit choose_tail_split(int tiles, int kiters, int slots, int max_units) {
+    TailSplit best;
+    if (tiles <= 0 || slots <= 0 || kiters < 8) return best;
+    best.full = tiles;
+    double best_cost = makespan(tiles, tiles, 1, slots);
+    // A split piece writes and re-reads one tile of partial sums: priced at 2/kiters of a
+    // whole tile's time per piece (the tile's own operand traffic is about kiters tile loads).
+    const double piece = 2.0 / kiters;
+    for (int full = (tiles / slots) * slots; full >= 0; full -= slots) {
+        for (int k = 2; k <= 4; ++k) {
+            const int units = (tiles - full) * k;
+            if (units <= 0 || units > max_units) continue;
+            const double cost = makespan(tiles, full, k, slots) + piece * units / slots;
+            if (cost < 0.97 * best_cost) {
+                best_cost = cost;
+                best.full = full;
+                best.k = k;
+            }
+        }
+        if (full == 0) break;
+    }
+    if (best.k == 1) best.full = tiles;
+    return best;
+}
+
+hipError_t gemm_launch_tail(Dt dt, const GemmProblem& p, TailSplit ts, void* ws, hipStream_t s) {
+    GemmProblem g[2] = {p, p};
+    if (ts.k <= 1 || !ws || p.ksplit > 1 || p.tile_off != 0 || p.tile_cnt >= 0) return gemm_launch(dt, g, 1, s);
+    g[0].tile_cnt = ts.full;
+    g[1].tile_off = ts.full;
+    g[1].ksplit = ts.k;
+    g[1].flags |= G_TILEPART;
+    g[1].partial = ws;
+    return gemm_launch(dt, g, 2, s);
 }
 
 }  // namespace kfmeg

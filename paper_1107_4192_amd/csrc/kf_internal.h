@@ -9,7 +9,7 @@
 namespace kfmeg {
 
 // ---------------------------------------------------------------- GEMM
-// C = alpha * op(A) op(B) + beta * Cin + gamma * Cin2.
+// C = alpha * op(A) op(B) + beta * Cin + gamma * Cin2 (gamma = 1 when Cin2 is given).
 // Operands are of the kernel's compute type (double or float); the epilogue is float64.
 enum GemmFlags : int {
     G_TA = 1,          // A(i,k) = A[k*lda + i]   (else A[i*lda + k])
@@ -23,6 +23,7 @@ enum GemmFlags : int {
     G_CIN2_32 = 256,   // Cin2 is float (else double)
     G_NXN = 512,       // separately named instantiation: smoother N x N x N products, float64 path
     G_NXN_MIXED = 1024,// separately named instantiation: the same products in the mixed-precision path
+    G_TILEPART = 2048, // with ksplit > 1: partial sums in one compact slice per tile (tile-wise reduction)
 };
 
 struct GemmProblem {
@@ -33,22 +34,16 @@ struct GemmProblem {
     const void* Cin = nullptr; int64_t ldcin = 0;
     const void* Cin2 = nullptr; int64_t ldcin2 = 0;
     double* C = nullptr; int64_t ldc = 0;       // float64 output (may be null)
-    float* C32 = nullptr; int64_t ldc32 = 0;    // float32 output (may be null)
+    float* C32 = nullptr; int64_t ldc32 = 0;    // float32 output (may be null; same ld as C when both)
     double* diag = nullptr;                     // C(i,i) for i < min(M,N) (may be null)
     int ksplit = 1;                             // >1: raw partial sums to `partial`, epilogue by gemm_reduce
-    void* partial = nullptr;                    // [ksplit][M][N], compute type
-    // filled by the launcher
-    int tiles_m = 0, tiles_n = 0, tile_begin = 0;
+    void* partial = nullptr;                    // [ksplit][M][N], or [tile][ksplit][BM*BN] with G_TILEPART
+    int tile_off = 0, tile_cnt = -1;            // run only tiles [tile_off, tile_off + tile_cnt) of the
+                                                // problem's tile order (-1: to the end)
 };
 
 constexpr int kMaxGroup = 16;
 constexpr int kMaxBatch = 8;   // matrices per batched factorisation (two problems each per group)
-struct GemmGroup {
-    GemmProblem p[kMaxGroup];
-    int count = 0;
-    int total_tiles = 0;
-    int remap = 1;     // group equal-cost tiles per XCD (off when K ranges vary per tile)
-};
 
 enum class Dt { F64, F32 };
 
@@ -56,6 +51,20 @@ enum class Dt { F64, F32 };
 // Problems with ksplit > 1 are followed by their reduction launch.
 hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s);
 inline hipError_t gemm1(Dt dt, GemmProblem p, hipStream_t s) { return gemm_launch(dt, &p, 1, s); }
+
+// Tail splitting of one large product: the first `full` tiles (in the problem's tile order)
+// run whole, the remaining ones split k ways along K with a tile-wise reduction, so that the
+// last wave of workgroups is not left mostly idle. `k == 1`: no split.
+struct TailSplit {
+    int full = 0, k = 1;
+};
+constexpr int kTileElems = 128 * 128;      // elements of one output tile
+int gemm_tiles(const GemmProblem& p);      // tiles of the problem's tile order
+int gemm_slots();                          // workgroups resident at once on the current device
+// Best split for `tiles` equal-cost tiles with `kiters` k-steps each, at most max_units split units.
+TailSplit choose_tail_split(int tiles, int kiters, int slots, int max_units);
+// Launch p with split ts; ws holds (tiles - full) * k tile slices of the compute type.
+hipError_t gemm_launch_tail(Dt dt, const GemmProblem& p, TailSplit ts, void* ws, hipStream_t s);
 
 // ---------------------------------------------------------------- Cholesky + inverse
 // Device status word: first failure wins. [0] = failed (1), [1] = which matrix, [2] = step t,

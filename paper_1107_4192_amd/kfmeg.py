@@ -23,7 +23,7 @@ _STATUS = {0: "KF_OK", 1: "KF_EINVAL", 2: "KF_ENOTPD", 3: "KF_ENOMEM", 4: "KF_EH
 EXPORTS = ("kf_default_options", "kf_create", "kf_filter", "kf_smooth", "kf_get_filtered_cov",
            "mne_solve", "kf_destroy", "kf_last_error", "kf_plan_bytes", "kfd_gemm", "kfd_chol_inv", "kf_set_profiling", "kf_get_profile",
            "kfs_create", "kfs_submit", "kfs_wait", "kfs_job_info", "kfs_get_stats", "kfs_last_error",
-           "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch")
+           "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch", "kfd_gemm_tail")
 
 
 class KFError(RuntimeError):
@@ -108,6 +108,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kfd_gemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, i64, dp,
                              i64, ctypes.c_double, ctypes.c_double, dp, i64, dp, i64, ctypes.c_int, vp]
     lib.kfd_gemm.restype = ctypes.c_int
+    lib.kfd_gemm_tail.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, i64, dp,
+                                  i64, ctypes.c_double, ctypes.c_double, dp, i64, dp, i64, ctypes.c_int, ctypes.c_int,
+                                  vp]
+    lib.kfd_gemm_tail.restype = ctypes.c_int
     lib.kfd_chol_inv.argtypes = [ctypes.c_int, dp, i64, dp, i64, ctypes.POINTER(ctypes.c_int), vp]
     lib.kfd_chol_inv.restype = ctypes.c_int
     _lib = lib
@@ -337,6 +341,20 @@ def kfd_gemm(A, B, M, N, K, flags=0, alpha=1.0, beta=0.0, Cin=None, C=None, kspl
                       C.data_ptr(), C.stride(0), ksplit, _stream_ptr(stream))
     if st != 0:
         raise KFError(st, "kfd_gemm failed")
+    return C
+
+
+def kfd_gemm_tail(A, B, M, N, K, flags=0, alpha=1.0, beta=0.0, Cin=None, C=None, full=0, k=2, stream=None):
+    """kfd_gemm with the first `full` tiles whole and the rest split k ways along K."""
+    lib = load_library()
+    dtype = 0 if A.dtype == torch.float64 else 1
+    if C is None:
+        C = torch.zeros((M, N), dtype=torch.float64, device=A.device)
+    st = lib.kfd_gemm_tail(dtype, M, N, K, flags, A.data_ptr(), A.stride(0), B.data_ptr(), B.stride(0), alpha, beta,
+                           Cin.data_ptr() if Cin is not None else None, Cin.stride(0) if Cin is not None else 0,
+                           C.data_ptr(), C.stride(0), full, k, _stream_ptr(stream))
+    if st != 0:
+        raise KFError(st, "kfd_gemm_tail failed")
     return C
 
 

@@ -91,6 +91,34 @@ def test_gemm_triangular_operands(dtype, n, k, padded):
     assert (C - ref).abs().max() <= tol * ref.abs().max()
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("flags", [0, F.G_TB, F.G_TA, F.G_TB | F.G_LOWER | F.G_MIRROR])
+@pytest.mark.parametrize("full,k", [(0, 2), (7, 3), (20, 4), (35, 2)])
+def test_gemm_tail_split(dtype, flags, full, k):
+    # 6 x 6 tiles (21 lower): whole tiles first, the rest split along K with a tile-wise reduction
+    M = N = 700
+    K = 530
+    g = torch.Generator().manual_seed(full * 13 + k + flags)
+    ta, tb = bool(flags & F.G_TA), bool(flags & F.G_TB)
+    A = torch.randn((K, M) if ta else (M, K), generator=g, dtype=torch.float64).to(dtype)
+    B = torch.randn((N, K) if tb else (K, N), generator=g, dtype=torch.float64).to(dtype)
+    Cin = torch.randn((M, N), generator=g, dtype=torch.float64)
+    tiles = 21 if flags & F.G_LOWER else 36
+    full = min(full, tiles)
+    ref = -0.5 * (_op(A.double(), ta) @ _op(B.double(), tb)) + 2.0 * Cin
+    C = F.kfd_gemm_tail(_padded(A), _padded(B), M, N, K, flags, -0.5, 2.0, Cin.cuda(), full=full, k=k).cpu()
+    whole = F.kfd_gemm(_padded(A), _padded(B), M, N, K, flags, -0.5, 2.0, Cin.cuda()).cpu()
+    tol = (1e-13 if dtype == torch.float64 else 2e-6) * K ** 0.5 * 4
+    if flags & F.G_LOWER:
+        low = torch.tril(torch.ones(M, N, dtype=torch.bool))
+        assert (C[low] - ref[low]).abs().max() <= tol * ref.abs().max()
+        assert torch.equal(C, C.T)
+    else:
+        assert (C - ref).abs().max() <= tol * ref.abs().max()
+    # whole tiles are the same computation as without splitting: bitwise equal there
+    assert torch.equal(C[:128, :128], whole[:128, :128]) or full == 0
+
+
 def test_gemm_padded_leading_dimension():
     g = torch.Generator().manual_seed(5)
     big = torch.randn(300, 400, generator=g, dtype=torch.float64)
