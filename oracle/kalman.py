@@ -36,7 +36,7 @@ import numpy as np
 import scipy.linalg as sla
 
 __all__ = ["kf_update", "kf_filter", "smoother_gain", "rts_smooth", "rts_step_columns", "mne_solve",
-           "init_from_mne"]
+           "init_from_mne", "bf_smooth_means"]
 
 
 def _chol(A: np.ndarray):
@@ -161,3 +161,44 @@ def init_from_mne(X, C, R, Y, reg: float = 0.0):
     Q = (Q + Q.T) / 2.0
     Q = Q + reg * np.eye(Q.shape[0])
     return J[0].copy(), Q
+
+
+def bf_smooth_means(X, Q, R, x0, P0, Y):
+    """Smoothed means only, by the backward information recursion (modified Bryson-Frazier).
+
+    Not in the paper: an alternative to eqn12 that reaches the same x_{t|T} without the
+    smoother gain A_t, so without inverting P_{t+1|t}. With lambda_{T+1} = 0 and, going back,
+        x_{t|T}  = x_{t|t} + P_{t|t} lambda_{t+1}
+        lambda_t = X^T S_t^-1 e_t + (I - K_t X)^T lambda_{t+1}
+    where e_t = y_t - X x_{t|t-1}, S_t and K_t are the innovation, its covariance and the
+    gain of eqn8 at step t. (Substituting A_t P_{t+1|t} = P_{t|t} into eqn12 gives the first
+    line; the second follows from P_{t|t} = (I - K_t X) P_{t|t-1}.) The forward pass is the
+    filter above, written out again so that e_t, S_t and K_t are at hand. Returns (T, N).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    T = Y.shape[0]
+    N = X.shape[1]
+    x = np.asarray(x0, dtype=np.float64).copy()
+    P = np.asarray(P0, dtype=np.float64).copy()
+    xf = np.empty((T, N))
+    Pf, e, Sf, K = [], [], [], []
+    for t in range(T):
+        P_pred = P + Q                                 # eqn7
+        S = X @ P_pred @ X.T + R                       # bracket of eqn8
+        cS = _chol(S)
+        Kt = sla.cho_solve(cS, X @ P_pred).T           # eqn8
+        et = Y[t] - X @ x                              # innovation of eqn10
+        x = x + Kt @ et                                # eqn10
+        P = P_pred - Kt @ X @ P_pred
+        P = (P + P.T) / 2.0
+        xf[t] = x
+        Pf.append(P)
+        e.append(et)
+        Sf.append(cS)
+        K.append(Kt)
+    xs = np.empty((T, N))
+    lam = np.zeros(N)
+    for t in range(T - 1, -1, -1):
+        xs[t] = xf[t] + Pf[t] @ lam
+        lam = X.T @ sla.cho_solve(Sf[t], e[t]) + (np.eye(N) - K[t] @ X).T @ lam
+    return xs

@@ -607,17 +607,22 @@ __global__ __launch_bounds__(NT) void gemm_tile_reduce_kernel(GemmDesc P) {
     decode_tile(P, P.tile_off + slot, bm, bn);
     const T* part = static_cast<const T*>(P.partial) + (int64_t)slot * P.ksplit * kTileElems;
     AV acc[4][4];
+    // slice by slice, so that each slice's 64 loads are in flight together
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int idx = ((a * 4 + b) * 4 + r) * NT + tid;
-                T v = part[idx];
-                for (int sp = 1; sp < P.ksplit; ++sp) v += part[(int64_t)sp * kTileElems + idx];
-                acc[a][b][r] = v;
-            }
+            for (int r = 0; r < 4; ++r) acc[a][b][r] = part[((a * 4 + b) * 4 + r) * NT + tid];
+    for (int sp = 1; sp < P.ksplit; ++sp) {
+        const T* sl = part + (int64_t)sp * kTileElems;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[a][b][r] += sl[((a * 4 + b) * 4 + r) * NT + tid];
+    }
     epilogue<T>(P, acc, bm * BM, bn * BN, 0, slot, tid, true);
 }
 

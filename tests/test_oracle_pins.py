@@ -325,3 +325,54 @@ def test_pins_catch_planted_mistakes(mutant):
     xs, Ps, _ = smooth(xf, Pf, p.Q)
     errs = [rel(a, b) for a, b in zip((xf, Pf, xs, Ps), bf)]
     assert max(errs) > 1e-6, errs
+
+
+# ---------------------------------------------------------------- smoothed means without A_t
+@pytest.mark.parametrize("seed,N,m,T", [(1, 1, 1, 5), (3, 5, 3, 6), (4, 8, 4, 6), (5, 4, 6, 3), (6, 20, 6, 10)])
+def test_bf_means_match_brute_force(seed, N, m, T):
+    p = synth.small_random(seed, N, m, T)
+    xs = oracle.bf_smooth_means(p.X, p.Q, p.R, p.x0, p.P0, p.Y)
+    bf = oracle.joint_posterior(p.X, p.Q, p.R, p.x0, p.P0, p.Y)
+    assert rel(xs, bf[2]) < 1e-11
+
+
+def test_bf_means_match_rts_on_tiny_workload():
+    p = synth.tiny(T=15)
+    xs = oracle.bf_smooth_means(p.X, p.Q, p.R, p.x0, p.P0, p.Y)
+    assert rel(xs, run(p)[3]) < 1e-10
+
+
+def test_bf_last_step_is_filter_and_zero_q_is_least_squares():
+    p = synth.small_random(13, 6, 4, 5)
+    xs = oracle.bf_smooth_means(p.X, p.Q, p.R, p.x0, p.P0, p.Y)
+    xf = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, p.Y)[0]
+    assert rel(xs[-1], xf[-1]) == 0.0                     # lambda_{T+1} = 0
+    xs0 = oracle.bf_smooth_means(p.X, np.zeros_like(p.Q), p.R, p.x0, p.P0, p.Y)
+    xf0 = oracle.kf_filter(p.X, np.zeros_like(p.Q), p.R, p.x0, p.P0, p.Y)[0]
+    assert rel(xs0, np.broadcast_to(xf0[-1], xs0.shape)) < 1e-11   # static state: every x_{t|T} = x_{T|T}
+
+
+def _bf_transposed(X, Q, R, x0, P0, Y):
+    # planted: (I - K X) instead of its transpose in the lambda recursion
+    T, N = Y.shape[0], X.shape[1]
+    x, P = np.array(x0, float), np.array(P0, float)
+    xf, Pf, e, Sf, Kg = np.empty((T, N)), [], [], [], []
+    for t in range(T):
+        Pp = P + Q
+        S = X @ Pp @ X.T + R
+        Kt = np.linalg.solve(S, X @ Pp).T
+        e.append(Y[t] - X @ x); Sf.append(S); Kg.append(Kt)
+        x = x + Kt @ e[-1]
+        P = Pp - Kt @ X @ Pp
+        xf[t] = x; Pf.append(P)
+    xs, lam = np.empty((T, N)), np.zeros(N)
+    for t in range(T - 1, -1, -1):
+        xs[t] = xf[t] + Pf[t] @ lam
+        lam = X.T @ np.linalg.solve(Sf[t], e[t]) + (np.eye(N) - Kg[t] @ X) @ lam
+    return xs
+
+
+def test_bf_pin_catches_planted_transpose():
+    p = synth.small_random(17, 5, 3, 6)
+    bf = oracle.joint_posterior(p.X, p.Q, p.R, p.x0, p.P0, p.Y)
+    assert rel(_bf_transposed(p.X, p.Q, p.R, p.x0, p.P0, p.Y), bf[2]) > 1e-6
