@@ -56,9 +56,12 @@ typedef struct {
     size_t hbm_budget_bytes;  /* cap on the covariance store; 0 = whatever is free */
     int checkpoint_stride;    /* keep every k-th P_{t|t} and recompute the rest in the
                                  backward pass; 0 = automatic (only if the store does not fit) */
+    int keep_gain_factors;    /* keep the factors of each step's gain (C_t = L_t^-1 X P_{t|t-1},
+                                 L_t^-1, L_t^-1 e_t) for kf_smooth_means: T_max (m N + m^2 + m)
+                                 doubles more; 0 = off */
 } kf_options;
 
-/* Defaults: KF_FP64, float64 store, no budget cap, automatic checkpointing. */
+/* Defaults: KF_FP64, float64 store, no budget cap, automatic checkpointing, no gain factors kept. */
 void kf_default_options(kf_options* opt);
 
 /*
@@ -121,6 +124,25 @@ kf_status kf_filter_batch(kf_plan* plan, int64_t B, int64_t T, const double* Y,
                           double* x_filt, double* Pdiag_filt);
 kf_status kf_smooth_batch(kf_plan* plan, int64_t B, double* x_smooth,
                           double* Pdiag_smooth, double* P_smooth);
+
+/*
+ * kf_smooth_means / kf_smooth_means_batch: the smoothed means x_{t|T} alone,
+ * without the smoother gain A_t of eqn11 and so without factorising any
+ * N x N matrix. They equal the means of eqn12 (read as in kf_smooth) in exact
+ * arithmetic, through the backward information recursion (modified
+ * Bryson-Frazier form): with lambda_{T+1} = 0, for t = T..1,
+ *   x_{t|T}  = x_{t|t} + P_{t|t} lambda_{t+1}
+ *   lambda_t = lambda_{t+1} + X^T L_t^-T (L_t^-1 e_t - C_t lambda_{t+1})
+ * where S_t = L_t L_t^T (eqn8), e_t the innovation of eqn10 and
+ * C_t = L_t^-1 X P_{t|t-1}. Per step this is one N x N matrix-vector product
+ * and O(m N) work instead of O(N^3).
+ *   x_smooth (T x N), or (B x T x N) for the batch form with the B of the
+ *            last filter call.
+ * Needs a plan created with keep_gain_factors (KF_ESTATE otherwise, or without
+ * a completed filter call). Diagonals of P_{t|T} are not produced.
+ */
+kf_status kf_smooth_means(kf_plan* plan, double* x_smooth);
+kf_status kf_smooth_means_batch(kf_plan* plan, int64_t B, double* x_smooth);
 
 /* Copy the stored filtered covariance P_{t|t} (1 <= t <= T) into P_out (N x N, device). */
 kf_status kf_get_filtered_cov(kf_plan* plan, int64_t t, double* P_out);

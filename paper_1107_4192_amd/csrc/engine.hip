@@ -86,6 +86,12 @@ struct kf_plan {
     // together as B-row products (buffers sized for bcap data sets, grown on demand)
     int64_t bcap = 0;
     double *Eb = nullptr, *Wb = nullptr, *Xb0 = nullptr, *Vb = nullptr;
+    // gain factors of every filter step for the mean-only smoother: C_t (m x ldN),
+    // L_t^-1 (m x ldm) and L_t^-1 e_t (wcap rows of ldm per step)
+    bool keep = false;
+    double *fac_C = nullptr, *fac_L = nullptr, *fac_w = nullptr;
+    int64_t wcap = 0;
+    std::vector<double*> bfac_w;            // per-data-set factor buffers grown past one data set
     std::string err;
     // profiling of the smoother's N x N x N products (event pairs around each launch)
     bool prof = false;
@@ -196,6 +202,12 @@ size_t tail_bytes(int64_t N, bool mix) {
     const size_t units = std::max<size_t>(a.k > 1 ? (size_t)(full - a.full) * a.k : 0,
                                           b.k > 1 ? (size_t)(low - b.full) * b.k : 0);
     return units * kTileElems * (mix ? 4 : 8);
+}
+
+// Gain factors kept for the mean-only smoother (one data set).
+size_t factor_bytes(int64_t N, int64_t m, int64_t T) {
+    const int64_t ldN = round_up(N, 16), ldm = round_up(m, 16);
+    return 8 * (size_t)T * ((size_t)m * ldN + (size_t)m * ldm + (size_t)ldm);
 }
 
 size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int gb) {
@@ -442,6 +454,7 @@ void kf_default_options(kf_options* opt) {
     opt->store_fp32 = 0;
     opt->hbm_budget_bytes = 0;
     opt->checkpoint_stride = 0;
+    opt->keep_gain_factors = 0;
 }
 
 size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt) {
@@ -452,7 +465,7 @@ size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt) {
     const int64_t ldN = round_up(N, 16);
     const int stride = o.checkpoint_stride > 0 ? o.checkpoint_stride : 1;
     return workspace_bytes(N, m, o.precision == KF_MIXED, o.store_fp32, stride, kMaxBatch) +
-           store_bytes(N, ldN, T, o.store_fp32, stride);
+           store_bytes(N, ldN, T, o.store_fp32, stride) + (o.keep_gain_factors ? factor_bytes(N, m, T) : 0);
 }
 
 }  // extern "C"
@@ -497,8 +510,10 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     }
     int stride = p->opt.checkpoint_stride > 0 ? p->opt.checkpoint_stride : 1;
     const bool mix = mixed(p);
+    p->keep = p->opt.keep_gain_factors != 0;
+    const size_t fac = p->keep ? factor_bytes(N, m, T_max) : 0;
     auto need = [&](int st, int gb) {
-        return workspace_bytes(N, m, mix, p->store32, st, gb) + store_bytes(N, p->ldN, T_max, p->store32, st);
+        return workspace_bytes(N, m, mix, p->store32, st, gb) + store_bytes(N, p->ldN, T_max, p->store32, st) + fac;
     };
     // Prefer storing every P_{t|t}; give up gain batching before checkpointing.
     int gb = kMaxBatch;
@@ -541,6 +556,12 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
         }
     }
     ALLOC(p->Ps[0], NN); ALLOC(p->Ps[1], NN);
+    if (p->keep) {
+        ALLOC(p->fac_C, (size_t)T_max * mN);
+        ALLOC(p->fac_L, (size_t)T_max * mm);
+        ALLOC(p->fac_w, (size_t)T_max * p->ldm);
+        p->wcap = 1;
+    }
     tail_splits(N, p->ts_m, p->ts_low);
     if (const size_t tb = tail_bytes(N, mix)) {
         if ((st = alloc_bytes(p, &p->tail_ws, tb)) != KF_OK) return fail(st);
@@ -618,7 +639,7 @@ size_t plan_bytes_ex(int64_t N, int64_t m, int64_t T, const kf_options* opt, int
     const int64_t ldN = round_up(N, 16);
     const int stride = o.checkpoint_stride > 0 ? o.checkpoint_stride : 1;
     return workspace_bytes(N, m, o.precision == KF_MIXED, o.store_fp32, stride, gb) +
-           store_bytes(N, ldN, T, o.store_fp32, stride);
+           store_bytes(N, ldN, T, o.store_fp32, stride) + (o.keep_gain_factors ? factor_bytes(N, m, T) : 0);
 }
 
 }  // namespace kfmeg
@@ -640,6 +661,21 @@ static kf_status filter_impl(kf_plan* p, int64_t B, int64_t T, const double* Y, 
     if (p->hstatus[0]) {
         p->err = "kf_filter: Y holds a non-finite value";
         return KF_EINVAL;
+    }
+    if (p->keep && B > p->wcap) {
+        if (p->arena) {
+            p->err = "several data sets per call are not available on a serving plan";
+            return KF_EINVAL;
+        }
+        double* w = nullptr;
+        if (hipMalloc(&w, (size_t)p->Tmax * B * p->ldm * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            p->err = "device allocation of the gain factors for " + std::to_string(B) + " data sets failed";
+            return KF_ENOMEM;
+        }
+        p->bfac_w.push_back(w);    // freed with the plan
+        p->fac_w = w;
+        p->wcap = B;
     }
     if (B == 1) {
         HIPCK(hipMemcpyAsync(p->xw, p->x0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -664,6 +700,12 @@ static kf_status filter_impl(kf_plan* p, int64_t B, int64_t T, const double* Y, 
         if (!direct && slot64(p) && kept(p, t, T)) {
             HIPCK(hipMemcpyAsync(slot_ptr(p, slot_of(p, t, T)), out64, slot_elems(p) * 8, hipMemcpyDeviceToDevice,
                                  s));
+        }
+        if (p->keep) {   // C_t, L_t^-1 and L_t^-1 e_t (one row per data set) for the mean-only smoother
+            HIPCK(hipMemcpyAsync(p->fac_C + t * m * p->ldN, p->Cm, (size_t)m * p->ldN * 8, hipMemcpyDeviceToDevice, s));
+            HIPCK(hipMemcpyAsync(p->fac_L + t * m * p->ldm, p->Lis, (size_t)m * p->ldm * 8, hipMemcpyDeviceToDevice, s));
+            HIPCK(hipMemcpyAsync(p->fac_w + t * p->wcap * p->ldm, B == 1 ? p->w : p->Wb,
+                                 (B == 1 ? (size_t)m : (size_t)B * p->ldm) * 8, hipMemcpyDeviceToDevice, s));
         }
         prev64 = out64;
     }
@@ -911,6 +953,93 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
     return st;
 }
 
+// Smoothed means alone for the B data sets of the last filter call (backward information
+// recursion): x_{t|T} = x_{t|t} + P_{t|t} lambda_{t+1},
+// lambda_t = lambda_{t+1} + X^T L_t^-T (L_t^-1 e_t - C_t lambda_{t+1}), lambda_T = 0 (0-based t).
+kf_status smooth_means_impl(kf_plan* p, int64_t B, double* xs) {
+    hipStream_t s = p->stream;
+    const int64_t T = p->T_done, N = p->N, m = p->m;
+    const int64_t ld = p->ldN, ldx = T * N;
+    const double* xf = p->xf_last;
+    TRY(ensure_batch(p, B));                       // Xb0 / Vb: lambda double buffer; Eb, Wb: m-vectors
+    double* lam[2] = {p->Xb0, p->Vb};
+    HIPCK(zero2d((int)B, (int)N, lam[T & 1], ld, s));
+    HIPCK(hipMemcpy2DAsync(xs + (T - 1) * N, ldx * 8, xf + (T - 1) * N, ldx * 8, N * 8, B, hipMemcpyDeviceToDevice,
+                           s));
+    const bool s32 = p->store32;
+    int64_t seg_lo = -1, seg_hi = -2;
+    for (int64_t t = T - 1; t >= 0; --t) {
+        const double* ln = lam[(t + 1) & 1];       // lambda_{t+1}
+        double* lc = lam[t & 1];                   // lambda_t
+        if (t < T - 1) {
+            // P_{t|t}: a stored slot, or recomputed from the checkpoint before it
+            const void* Pt;
+            bool p32;
+            if (kept(p, t, T)) {
+                Pt = slot_ptr(p, slot_of(p, t, T));
+                p32 = !slot64(p);
+            } else {
+                if (t < seg_lo || t > seg_hi) {
+                    seg_lo = (t + 1) / p->stride * p->stride;
+                    seg_hi = t;
+                    TRY(recompute_segment(p, seg_lo, seg_hi, T));
+                }
+                Pt = static_cast<char*>(p->seg) + (size_t)(t - seg_lo) * slot_elems(p) * (s32 ? 4 : 8);
+                p32 = s32;
+            }
+            // A float32 store holds P_{t|t} rounded to float32 (a float64 checkpoint too)
+            if (s32 && (!p32 || B > 1)) {
+                HIPCK(copy2d_r32((int)N, (int)N, p->Pw[0], ld, Pt, p32, ld, s));
+                Pt = p->Pw[0];
+                p32 = false;
+            }
+            if (B == 1) {
+                HIPCK(gemv_add(Pt, p32, ld, ln, xf + t * N, xs + t * N, (int)N, s));
+            } else {
+                GemmProblem g;                     // X_{t|T} = X_{t|t} + Lambda_{t+1} P_{t|t}  (P symmetric)
+                g.M = (int)B; g.N = (int)N; g.K = (int)N;
+                g.A = ln; g.lda = ld; g.B = Pt; g.ldb = ld; g.flags = G_TB;
+                g.Cin = xf + t * N; g.ldcin = ldx; g.beta = 1.0;
+                g.C = xs + t * N; g.ldc = ldx;
+                g.ksplit = batch_ksplit(p, B, N, 4);
+                g.partial = p->partial;
+                HIPCK(gemm1(Dt::F64, g, s));
+            }
+        }
+        if (t == 0) break;                         // lambda_0 is not needed
+        const double* C = p->fac_C + t * m * p->ldN;
+        const double* L = p->fac_L + t * m * p->ldm;
+        const double* w = p->fac_w + t * p->wcap * p->ldm;
+        if (B == 1) {
+            HIPCK(resid(C, p->ldN, ln, w, p->e, (int)m, (int)N, s));           // v = L^-1 e - C lambda
+            HIPCK(trmv_lower_t(L, p->ldm, p->e, p->w, (int)m, s));            // u = L^-T v
+            HIPCK(gemv_t_add(p->X, p->ldN, p->w, ln, lc, nullptr, (int)m, (int)N, s));   // lambda += X^T u
+        } else {
+            GemmProblem g;                         // V = W_t - Lambda C_t^T
+            g.M = (int)B; g.N = (int)m; g.K = (int)N;
+            g.A = ln; g.lda = ld; g.B = C; g.ldb = p->ldN; g.flags = G_TB;
+            g.alpha = -1.0;
+            g.Cin = w; g.ldcin = p->ldm; g.beta = 1.0;
+            g.C = p->Eb; g.ldc = p->ldm;
+            g.ksplit = batch_ksplit(p, B, m, std::max(1, std::min(16, (int)N / 256)));
+            g.partial = p->partial;
+            HIPCK(gemm1(Dt::F64, g, s));
+            GemmProblem h;                         // U = V L^-1  (rows: L^-T v_b)
+            h.M = (int)B; h.N = (int)m; h.K = (int)m;
+            h.A = p->Eb; h.lda = p->ldm; h.B = L; h.ldb = p->ldm; h.flags = G_BLOWER;
+            h.C = p->Wb; h.ldc = p->ldm;
+            HIPCK(gemm1(Dt::F64, h, s));
+            GemmProblem u;                         // Lambda_t = Lambda_{t+1} + U X
+            u.M = (int)B; u.N = (int)N; u.K = (int)m;
+            u.A = p->Wb; u.lda = p->ldm; u.B = p->X; u.ldb = p->ldN;
+            u.Cin = ln; u.ldcin = ld; u.beta = 1.0;
+            u.C = lc; u.ldc = ld;
+            HIPCK(gemm1(Dt::F64, u, s));
+        }
+    }
+    return sync_and_check(p, "kf_smooth_means");
+}
+
 }  // namespace
 
 extern "C" {
@@ -937,6 +1066,31 @@ kf_status kf_smooth_batch(kf_plan* p, int64_t B, double* x_smooth, double* Pdiag
 kf_status kf_smooth(kf_plan* p, double* x_smooth, double* Pdiag_smooth, double* P_smooth) {
     return kf_smooth_batch(p, 1, x_smooth, Pdiag_smooth, P_smooth);
 }
+
+kf_status kf_smooth_means_batch(kf_plan* p, int64_t B, double* x_smooth) {
+    if (!p) return KF_EINVAL;
+    p->err.clear();
+    if (!p->keep) {
+        p->err = "kf_smooth_means: the plan was created without keep_gain_factors";
+        return KF_ESTATE;
+    }
+    if (p->T_done <= 0 || !p->xf_last) {
+        p->err = "kf_smooth_means: no completed kf_filter on this plan";
+        return KF_ESTATE;
+    }
+    if (B != p->B_done) {
+        p->err = "kf_smooth_means: the last filter call ran " + std::to_string(p->B_done) + " data set(s), not " +
+                 std::to_string(B);
+        return KF_ESTATE;
+    }
+    if (!x_smooth) {
+        p->err = "kf_smooth_means: x_smooth is null";
+        return KF_EINVAL;
+    }
+    return smooth_means_impl(p, B, x_smooth);
+}
+
+kf_status kf_smooth_means(kf_plan* p, double* x_smooth) { return kf_smooth_means_batch(p, 1, x_smooth); }
 
 kf_status kf_get_filtered_cov(kf_plan* p, int64_t t, double* P_out) {
     if (!p) return KF_EINVAL;
@@ -997,6 +1151,7 @@ void kf_destroy(kf_plan* p) {
     if (p->s2) (void)hipStreamDestroy(p->s2);
     for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb})
         if (b) (void)hipFree(b);
+    for (double* b : p->bfac_w) (void)hipFree(b);
     for (void* a : p->allocs) {
         if (p->arena) p->arena->release(a);
         else (void)hipFree(a);

@@ -93,6 +93,11 @@ hipError_t gemv_t_add(const double* C, int64_t ldc, const double* w, const doubl
 // out = x + A (v - x)   (A: N x N, ld lda)   -- smoothed mean (eqn12)
 hipError_t gemv_smooth(const double* A, int64_t lda, const double* x, const double* v,
                        double* out, int N, hipStream_t s);
+// out = x + P lam  (P: N x N float or double, ld ldp)   -- mean-only smoother
+hipError_t gemv_add(const void* P, bool p32, int64_t ldp, const double* lam, const double* x, double* out, int N,
+                    hipStream_t s);
+// u = Lower(L)^T v  (L: m x m, ld ldl)
+hipError_t trmv_lower_t(const double* L, int64_t ldl, const double* v, double* u, int m, hipStream_t s);
 // D = a + ca*b + cb*c for matrices (rows x cols); each source may be float or double
 hipError_t axpby3(int rows, int cols, void* D, bool d32, int64_t ldd,
                   const void* a, bool a32, int64_t lda,

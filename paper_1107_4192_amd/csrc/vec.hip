@@ -90,6 +90,36 @@ __global__ void gemv_smooth_kernel(const double* A, int64_t lda, const double* x
     if (lane == 0) out[row] = x[row] + s;
 }
 
+// out_i = x_i + sum_k P[i][k] lam_k (P float or double); one wave per row, four partial sums
+// per lane combined in a fixed order.
+template <typename TP>
+__global__ void gemv_add_kernel(const TP* P, int64_t ldp, const double* lam, const double* x, double* out, int N) {
+    const int row = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= N) return;
+    const TP* pr = P + (int64_t)row * ldp;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = lane;
+    for (; k + 192 < N; k += 256) {
+        s0 += (double)pr[k] * lam[k];
+        s1 += (double)pr[k + 64] * lam[k + 64];
+        s2 += (double)pr[k + 128] * lam[k + 128];
+        s3 += (double)pr[k + 192] * lam[k + 192];
+    }
+    for (; k < N; k += 64) s0 += (double)pr[k] * lam[k];
+    const double s = wave_sum((s0 + s1) + (s2 + s3));
+    if (lane == 0) out[row] = x[row] + s;
+}
+
+// u_i = sum_{k >= i} L[k][i] v_k  (L lower, m x m): u = L^T v, one thread per i.
+__global__ void trmv_lower_t_kernel(const double* L, int64_t ldl, const double* v, double* u, int m) {
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int k = i; k < m; ++k) s += L[(int64_t)k * ldl + i] * v[k];
+    u[i] = s;
+}
+
 // Elementwise sweeps over a rows x cols block: blockIdx.y walks the rows, the x dimension
 // the columns, so consecutive lanes touch consecutive elements and no index is divided.
 template <typename TD, typename TA, typename TB, typename TC>
@@ -241,6 +271,22 @@ hipError_t gemv_t_add(const double* C, int64_t ldc, const double* w, const doubl
 hipError_t gemv_smooth(const double* A, int64_t lda, const double* x, const double* v, double* out, int N,
                        hipStream_t s) {
     hipLaunchKernelGGL(gemv_smooth_kernel, dim3((N + 3) / 4), dim3(TPB), 0, s, A, lda, x, v, out, N);
+    return hipGetLastError();
+}
+
+hipError_t gemv_add(const void* P, bool p32, int64_t ldp, const double* lam, const double* x, double* out, int N,
+                    hipStream_t s) {
+    if (p32)
+        hipLaunchKernelGGL(gemv_add_kernel<float>, dim3((N + 3) / 4), dim3(TPB), 0, s, static_cast<const float*>(P), ldp,
+                           lam, x, out, N);
+    else
+        hipLaunchKernelGGL(gemv_add_kernel<double>, dim3((N + 3) / 4), dim3(TPB), 0, s, static_cast<const double*>(P),
+                           ldp, lam, x, out, N);
+    return hipGetLastError();
+}
+
+hipError_t trmv_lower_t(const double* L, int64_t ldl, const double* v, double* u, int m, hipStream_t s) {
+    hipLaunchKernelGGL(trmv_lower_t_kernel, dim3((m + TPB - 1) / TPB), dim3(TPB), 0, s, L, ldl, v, u, m);
     return hipGetLastError();
 }
 

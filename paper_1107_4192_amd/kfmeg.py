@@ -23,7 +23,8 @@ _STATUS = {0: "KF_OK", 1: "KF_EINVAL", 2: "KF_ENOTPD", 3: "KF_ENOMEM", 4: "KF_EH
 EXPORTS = ("kf_default_options", "kf_create", "kf_filter", "kf_smooth", "kf_get_filtered_cov",
            "mne_solve", "kf_destroy", "kf_last_error", "kf_plan_bytes", "kfd_gemm", "kfd_chol_inv", "kf_set_profiling", "kf_get_profile",
            "kfs_create", "kfs_submit", "kfs_wait", "kfs_job_info", "kfs_get_stats", "kfs_last_error",
-           "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch", "kfd_gemm_tail")
+           "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch", "kfd_gemm_tail", "kf_smooth_means",
+           "kf_smooth_means_batch")
 
 
 class KFError(RuntimeError):
@@ -45,7 +46,8 @@ class kfs_stats(ctypes.Structure):
 
 class kf_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("store_fp32", ctypes.c_int),
-                ("hbm_budget_bytes", ctypes.c_size_t), ("checkpoint_stride", ctypes.c_int)]
+                ("hbm_budget_bytes", ctypes.c_size_t), ("checkpoint_stride", ctypes.c_int),
+                ("keep_gain_factors", ctypes.c_int)]
 
 
 _lib = None
@@ -69,6 +71,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_filter.restype = ctypes.c_int
     lib.kf_smooth.argtypes = [vp, dp, dp, dp]
     lib.kf_smooth.restype = ctypes.c_int
+    lib.kf_smooth_means.argtypes = [vp, dp]
+    lib.kf_smooth_means.restype = ctypes.c_int
+    lib.kf_smooth_means_batch.argtypes = [vp, i64, dp]
+    lib.kf_smooth_means_batch.restype = ctypes.c_int
     lib.kf_filter_batch.argtypes = [vp, i64, i64, dp, dp, dp]
     lib.kf_filter_batch.restype = ctypes.c_int
     lib.kf_smooth_batch.argtypes = [vp, i64, dp, dp, dp]
@@ -148,8 +154,9 @@ def _check(lib, st: int, plan=None):
 
 
 def options(precision: int = KF_FP64, store_fp32: bool = False, hbm_budget_bytes: int = 0,
-            checkpoint_stride: int = 0) -> kf_options:
-    return kf_options(int(precision), int(bool(store_fp32)), int(hbm_budget_bytes), int(checkpoint_stride))
+            checkpoint_stride: int = 0, keep_gain_factors: bool = False) -> kf_options:
+    return kf_options(int(precision), int(bool(store_fp32)), int(hbm_budget_bytes), int(checkpoint_stride),
+                      int(bool(keep_gain_factors)))
 
 
 def kf_plan_bytes(N: int, m: int, T: int, opt: kf_options | None = None) -> int:
@@ -204,6 +211,16 @@ def kf_smooth_batch(plan: int, x_smooth, Pdiag_smooth=None, P_smooth=None) -> No
     st = lib.kf_smooth_batch(plan, B, _dev(x_smooth, "x_smooth", (B, T, N)),
                              _dev(Pdiag_smooth, "Pdiag_smooth", (T, N)) if Pdiag_smooth is not None else None,
                              _dev(P_smooth, "P_smooth", (T, N, N)) if P_smooth is not None else None)
+    _check(lib, st, plan)
+
+
+def kf_smooth_means(plan: int, x_smooth) -> None:
+    """Smoothed means only (backward information recursion); x_smooth (T, N) or (B, T, N)."""
+    lib = load_library()
+    if x_smooth.dim() == 2:
+        st = lib.kf_smooth_means(plan, _dev(x_smooth, "x_smooth", tuple(x_smooth.shape)))
+    else:
+        st = lib.kf_smooth_means_batch(plan, x_smooth.shape[0], _dev(x_smooth, "x_smooth", tuple(x_smooth.shape)))
     _check(lib, st, plan)
 
 
@@ -385,10 +402,11 @@ class KalmanSmoother:
     """Convenience wrapper owning one plan: ``run(Y)`` = kf_filter + kf_smooth."""
 
     def __init__(self, X, Q, R, x0, P0, T_max: int, precision: int = KF_FP64, store_fp32: bool = False,
-                 hbm_budget_bytes: int = 0, checkpoint_stride: int = 0, stream=None):
+                 hbm_budget_bytes: int = 0, checkpoint_stride: int = 0, keep_gain_factors: bool = False,
+                 stream=None):
         self.m, self.N = X.shape
         self.T_max = T_max
-        self.opt = options(precision, store_fp32, hbm_budget_bytes, checkpoint_stride)
+        self.opt = options(precision, store_fp32, hbm_budget_bytes, checkpoint_stride, keep_gain_factors)
         self.plan = kf_create(self.N, self.m, T_max, X, Q, R, x0, P0, self.opt, stream)
 
     def filter(self, Y, want_diag: bool = True) -> Result:
@@ -409,6 +427,12 @@ class KalmanSmoother:
 
     def run(self, Y, want_full: bool = False) -> Result:
         return self.smooth(self.filter(Y), want_full=want_full)
+
+    def smooth_means(self, res: Result) -> Result:
+        """x_{t|T} only (needs keep_gain_factors); res.x_filt from the last filter call."""
+        res.x_smooth = torch.empty_like(res.x_filt)
+        kf_smooth_means(self.plan, res.x_smooth)
+        return res
 
     def run_batch(self, Y, want_diag: bool = True) -> Result:
         """Filter and smooth B data sets, Y: (B, T, m); means come back as (B, T, N)."""
