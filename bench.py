@@ -13,6 +13,10 @@ Besides the contract's JSON fields the line carries:
                 of the same workload at full N: filter 10 steps + smoother 9 steps);
   mixed         the same workload in mixed precision (FP32 MFMA bulk, FP64 factorisations,
                 FP32 store): its rate, speedup over FP64 and its error against the FP64 path;
+  mean_only     kf_filter + kf_smooth_means (smoothed means without P_{t|T}) on the same
+                workload, and its difference from the full smoother's means;
+  batched       eight data sets of the same model through one covariance pass
+                (kf_filter_batch + kf_smooth_batch), in data-set time-steps/s;
   serving       p50/p99 job latency and throughput of the continuous-batching server on a
                 Poisson stream of jobs of mixed N, m, T, against the same jobs run one at a
                 time in FP64.
@@ -132,6 +136,64 @@ def run_gpu(p, precision, steps, warmup, store_fp32=False, profile=False):
     return out
 
 
+def run_mean_only(p, steps, xs_ref):
+    """kf_filter + kf_smooth_means (backward information recursion) on the same workload."""
+    import numpy as np
+    import torch
+    from paper_1107_4192_amd import kfmeg
+
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    X, Q, R, x0, P0, Y = (dev(a) for a in (p.X, p.Q, p.R, p.x0, p.P0, p.Y))
+    ks = kfmeg.KalmanSmoother(X, Q, R, x0, P0, T_max=p.T, keep_gain_factors=True)
+    xf = torch.empty((p.T, p.N), dtype=torch.float64, device="cuda")
+    xs = torch.empty_like(xf)
+    kfmeg.kf_filter(ks.plan, Y, xf)
+    kfmeg.kf_smooth_means(ks.plan, xs)
+    torch.cuda.synchronize()
+    t_f = t_s = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        kfmeg.kf_filter(ks.plan, Y, xf)
+        b = time.perf_counter()
+        kfmeg.kf_smooth_means(ks.plan, xs)
+        c = time.perf_counter()
+        t_f += b - a
+        t_s += c - b
+    elapsed = time.perf_counter() - t0
+    ref = xs_ref.cpu().numpy()
+    err = float(np.linalg.norm(xs.cpu().numpy() - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
+    ks.close()
+    log(f"mean-only: {p.T * steps / elapsed:.1f} steps/s")
+    return {"value": p.T * steps / elapsed, "unit": "time-steps/s", "filter_s_per_pass": t_f / steps,
+            "smoother_s_per_pass": t_s / steps, "eps_x_smooth_vs_rts_path": err,
+            "what": "kf_filter + kf_smooth_means: smoothed means only, no P_{t|T}"}
+
+
+def run_batched(p, B, steps):
+    """B data sets through one covariance pass (kf_filter_batch + kf_smooth_batch)."""
+    import numpy as np
+    import torch
+    from paper_1107_4192_amd import kfmeg
+
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(11)
+    Ys = np.stack([p.Y] + [p.Y + np.std(p.Y) * rng.normal(size=p.Y.shape) for _ in range(B - 1)])
+    X, Q, R, x0, P0, Yd = (dev(a) for a in (p.X, p.Q, p.R, p.x0, p.P0, Ys))
+    ks = kfmeg.KalmanSmoother(X, Q, R, x0, P0, T_max=p.T)
+    ks.run_batch(Yd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ks.run_batch(Yd)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ks.close()
+    log(f"batched B={B}: {B * p.T * steps / elapsed:.1f} data-set steps/s")
+    return {"B": B, "value": B * p.T * steps / elapsed, "unit": "data-set time-steps/s",
+            "s_per_pass": elapsed / steps}
+
+
 def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(102, 204, 306),
                 T_range=(20, 60), max_active=4):
     """Serving form: Poisson arrivals of filter+smoother jobs of mixed shapes, mixed precision
@@ -238,6 +300,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 256 MiB copy first (HBM counter scale)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mean-only and batched legs")
     ap.add_argument("--workload", choices=("paper", "free"), default="paper",
                     help="free: run the free-orientation N=15372 workload only (full store and checkpointed)")
     args = ap.parse_args()
@@ -301,6 +364,9 @@ def main():
                          "eps_x_smooth_vs_fp64_path": ex, "eps_diagP_smooth_vs_fp64_path": ed,
                          "store": "fp32", "filter_s_per_pass": rmx["t_filter"],
                          "smoother_s_per_pass": rmx["t_smooth"]}
+    if not args.no_extra:
+        line["mean_only"] = run_mean_only(p, max(1, args.steps), r64["x_smooth"])
+        line["batched"] = run_batched(p, 8, 1)
     if not args.no_serving:
         line["serving"] = run_serving()
     if not args.no_cpu:
