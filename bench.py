@@ -48,18 +48,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_nxn_f64_paper_N5124_traffic.
 GEMM_SOURCE = os.path.join(ROOT, "paper_1107_4192_amd", "csrc", "gemm.hip")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter runs, or None if the
-    kernel source changed since they were taken."""
+def measured_traffic(flops_per_launch):
+    """HBM bytes per launch of the dominant kernel: bytes per algorithmic flop from the committed
+    counter runs times this run's flops per launch; None if the kernel source changed since."""
     import hashlib
     try:
         d = json.load(open(TRAFFIC_FILE))
         h = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if d.get("gemm_source_sha256") != h:
+    if d.get("gemm_source_sha256") != h or not d.get("bytes_per_flop"):
         return None
-    return d.get("bytes_per_launch")
+    return d["bytes_per_flop"] * flops_per_launch
 
 
 def calibration_copy():
@@ -347,7 +347,7 @@ def main():
                    "N": p.N, "m": p.m, "T": p.T, "precision": "fp64", "store": "fp64",
                    "filter_s_per_pass": r64["t_filter"], "smoother_s_per_pass": r64["t_smooth"]},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_F64 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_F64, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_F64, "traffic": measured_traffic(kflops / max(launches, 1)),
                      "kernel": KERNEL + " (smoother N x N x N products: A_t factors and eqn13)",
                      "launches": launches, "avg_launch_ms": kms / max(launches, 1),
                      "flops_per_launch": kflops / max(launches, 1)},

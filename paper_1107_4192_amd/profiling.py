@@ -1,12 +1,16 @@
 """Turn rocprofv3 CSV output into the short summaries kept under profiles/.
 
     python -m paper_1107_4192_amd.profiling stats <run_kernel_stats.csv> [top]
-    python -m paper_1107_4192_amd.profiling traffic <fetch counter csv> <write counter csv> <kernel> <out.json>
+    python -m paper_1107_4192_amd.profiling traffic <fetch counter csv> <write counter csv> <kernel> <out.json> \
+        [bench log of the counter run]
 
 ``traffic`` scales the per-dispatch FETCH_SIZE and WRITE_SIZE of `kernel` by what
 the same counters read for the plain 256 MiB device copy that ``bench.py
 --calib-copy`` runs first (rocclr's copyBuffer), and records the SHA-256 of the
-GEMM source so that a stale figure is recognised.
+GEMM source so that a stale figure is recognised. Given the counter run's bench log
+(its JSON line carries the algorithmic flops of the same dispatches), it also records
+HBM bytes per algorithmic flop, which ``bench.py`` scales to the flops per launch of
+its own run (whose mix of launches differs from the short counter run's).
 """
 from __future__ import annotations
 
@@ -39,7 +43,15 @@ def _per_kernel(path: str, counter: str):
     return out
 
 
-def traffic(fetch_csv: str, write_csv: str, kernel: str) -> dict:
+def _bench_flops(log_path: str) -> float:
+    for line in open(log_path):
+        if line.startswith("{"):
+            r = json.loads(line)["roofline"]
+            return float(r["flops_per_launch"]) * int(r["launches"])
+    raise ValueError(f"no bench JSON line in {log_path}")
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, bench_log: str | None = None) -> dict:
     f, w = _per_kernel(fetch_csv, "FETCH_SIZE"), _per_kernel(write_csv, "WRITE_SIZE")
     # the copy reads and writes COPY_BYTES: the largest dispatches of the copy kernel are the calibration
     fcopy = max(f[COPY_KERNEL]) * 1024.0
@@ -61,6 +73,7 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str) -> dict:
         "bytes_per_launch": sum(per) / n,
         "per_dispatch_bytes": per,
         "gemm_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+        "bytes_per_flop": (sum(per) / _bench_flops(bench_log)) if bench_log else None,
     }
 
 
@@ -68,7 +81,7 @@ def main(argv):
     if argv[1] == "stats":
         print(kernel_stats_summary(argv[2], int(argv[3]) if len(argv) > 3 else 15))
     elif argv[1] == "traffic":
-        d = traffic(argv[2], argv[3], argv[4])
+        d = traffic(argv[2], argv[3], argv[4], argv[6] if len(argv) > 6 else None)
         with open(argv[5], "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps({k: v for k, v in d.items() if k != "per_dispatch_bytes"}, indent=1))
