@@ -41,7 +41,8 @@ typedef enum {
     KF_ENOTPD = 2,   /* S or P_{t+1|t} not positive definite (step and matrix in the message) */
     KF_ENOMEM = 3,   /* device allocation failed or the HBM budget is too small */
     KF_EHIP = 4,     /* a HIP runtime call failed */
-    KF_ESTATE = 5    /* call out of order (kf_smooth before a completed kf_filter) */
+    KF_ESTATE = 5,   /* call out of order (kf_smooth before a completed kf_filter) */
+    KF_ECANCELED = 6 /* serving: the job was cancelled before it started */
 } kf_status;
 
 typedef enum {
@@ -217,6 +218,9 @@ size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt);
  * kfs_wait blocks until the job is done and returns its status (KF_ENOTPD,
  * KF_ENOMEM if it can never fit the budget, ...); latency_ms = completion minus
  * submission.
+ * kfs_cancel removes a job that has not started yet: its kfs_wait returns
+ * KF_ECANCELED and its buffers are free at once. A job that is running or done
+ * is not interrupted (KF_ESTATE); KF_EINVAL for an unknown id.
  * kfs_get_stats: latency percentiles over completed jobs, throughput over the
  * span from the first submission to the last completion, peak arena use (never
  * above the budget) and the most jobs that ran at once.
@@ -229,6 +233,7 @@ typedef struct {
     int64_t submitted, completed, failed, checkpointed;
     size_t peak_bytes, budget_bytes;
     int max_concurrent;
+    int64_t canceled;
 } kfs_stats;
 
 kf_status kfs_create(kfs_server** out, size_t hbm_budget_bytes, int max_active, const kf_options* opt);
@@ -236,6 +241,7 @@ kf_status kfs_submit(kfs_server* srv, int64_t N, int64_t m, int64_t T, const dou
                      const double* R, const double* x0, const double* P0, const double* Y,
                      double* x_smooth, double* Pdiag_smooth, int64_t* job_id);
 kf_status kfs_wait(kfs_server* srv, int64_t job_id, double* latency_ms);
+kf_status kfs_cancel(kfs_server* srv, int64_t job_id);
 kf_status kfs_job_info(kfs_server* srv, int64_t job_id, int* done, int* checkpoint_stride,
                        double* queued_ms, double* run_ms);
 kf_status kfs_get_stats(kfs_server* srv, kfs_stats* out);

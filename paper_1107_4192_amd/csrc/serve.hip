@@ -99,7 +99,7 @@ struct kfs_server {
     int64_t next_id = 1;
     size_t reserved = 0;
     int active = 0, max_conc = 0;
-    int64_t completed = 0, failed = 0, checkpointed = 0, retry_after = -1;
+    int64_t completed = 0, failed = 0, checkpointed = 0, canceled = 0, retry_after = -1;
     std::vector<double> latencies;
     int64_t steps_done = 0;
     Clock::time_point first_arrival, last_end;
@@ -224,6 +224,7 @@ kf_status kfs_create(kfs_server** out, size_t hbm_budget_bytes, int max_active, 
     if (opt) s->opt = *opt;
     s->opt.checkpoint_stride = 0;
     s->opt.hbm_budget_bytes = 0;
+    s->opt.keep_gain_factors = 0;        // jobs run the full smoother
     (void)hipGetDevice(&s->device);
     size_t budget = hbm_budget_bytes;
     if (budget == 0) {
@@ -279,6 +280,24 @@ kf_status kfs_wait(kfs_server* s, int64_t job_id, double* latency_ms) {
     return j->status;
 }
 
+kf_status kfs_cancel(kfs_server* s, int64_t job_id) {
+    if (!s) return KF_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end()) return KF_EINVAL;
+    Job* j = it->second.get();
+    auto q = std::find(s->queue.begin(), s->queue.end(), j);
+    if (q == s->queue.end()) return KF_ESTATE;     // running or finished
+    s->queue.erase(q);
+    j->done = true;
+    j->status = KF_ECANCELED;
+    j->err = "job cancelled before it started";
+    j->end = Clock::now();
+    ++s->canceled;
+    s->cv.notify_all();
+    return KF_OK;
+}
+
 kf_status kfs_job_info(kfs_server* s, int64_t job_id, int* done, int* checkpoint_stride, double* queued_ms,
                        double* run_ms) {
     if (!s) return KF_EINVAL;
@@ -322,6 +341,7 @@ kf_status kfs_get_stats(kfs_server* s, kfs_stats* out) {
     out->peak_bytes = s->arena.peak();
     out->budget_bytes = s->budget;
     out->max_concurrent = s->max_conc;
+    out->canceled = s->canceled;
     return KF_OK;
 }
 

@@ -15,16 +15,17 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkfmeg.so")
 
-KF_OK, KF_EINVAL, KF_ENOTPD, KF_ENOMEM, KF_EHIP, KF_ESTATE = range(6)
+KF_OK, KF_EINVAL, KF_ENOTPD, KF_ENOMEM, KF_EHIP, KF_ESTATE, KF_ECANCELED = range(7)
 KF_FP64, KF_MIXED = 0, 1
-_STATUS = {0: "KF_OK", 1: "KF_EINVAL", 2: "KF_ENOTPD", 3: "KF_ENOMEM", 4: "KF_EHIP", 5: "KF_ESTATE"}
+_STATUS = {0: "KF_OK", 1: "KF_EINVAL", 2: "KF_ENOTPD", 3: "KF_ENOMEM", 4: "KF_EHIP", 5: "KF_ESTATE",
+           6: "KF_ECANCELED"}
 
 # Every function the header declares; a CPU test checks the library exports them all.
 EXPORTS = ("kf_default_options", "kf_create", "kf_filter", "kf_smooth", "kf_get_filtered_cov",
            "mne_solve", "kf_destroy", "kf_last_error", "kf_plan_bytes", "kfd_gemm", "kfd_chol_inv", "kf_set_profiling", "kf_get_profile",
            "kfs_create", "kfs_submit", "kfs_wait", "kfs_job_info", "kfs_get_stats", "kfs_last_error",
            "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch", "kfd_gemm_tail", "kf_smooth_means",
-           "kf_smooth_means_batch")
+           "kf_smooth_means_batch", "kfs_cancel")
 
 
 class KFError(RuntimeError):
@@ -38,7 +39,7 @@ class kfs_stats(ctypes.Structure):
                 ("max_ms", ctypes.c_double), ("jobs_per_s", ctypes.c_double), ("steps_per_s", ctypes.c_double),
                 ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("checkpointed", ctypes.c_int64), ("peak_bytes", ctypes.c_size_t),
-                ("budget_bytes", ctypes.c_size_t), ("max_concurrent", ctypes.c_int)]
+                ("budget_bytes", ctypes.c_size_t), ("max_concurrent", ctypes.c_int), ("canceled", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -102,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kfs_submit.restype = ctypes.c_int
     lib.kfs_wait.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
     lib.kfs_wait.restype = ctypes.c_int
+    lib.kfs_cancel.argtypes = [vp, i64]
+    lib.kfs_cancel.restype = ctypes.c_int
     lib.kfs_job_info.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.kfs_job_info.restype = ctypes.c_int
@@ -319,6 +322,14 @@ class Server:
             msg = self._lib.kfs_last_error(self.h)
             raise KFError(st, msg.decode() if msg else "")
         return bufs[6], bufs[7], lat.value
+
+    def cancel(self, job_id: int) -> bool:
+        """Remove a job that has not started; False if it is already running or done."""
+        st = self._lib.kfs_cancel(self.h, job_id)
+        if st == KF_ESTATE:
+            return False
+        _check(self._lib, st)
+        return True
 
     def info(self, job_id: int) -> dict:
         d, s, q, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_double()

@@ -101,3 +101,23 @@ def test_job_that_never_fits_is_rejected():
         assert ei.value.status == kfmeg.KF_ENOMEM
     finally:
         srv.close()
+
+
+def test_cancel_queued_job():
+    # one slot: the long first job keeps the others queued while the last one is cancelled
+    jobs = make_jobs([(1500, 100, 20), (200, 30, 6), (260, 45, 9), (250, 30, 8)], seed0=500)
+    srv = kfmeg.Server(max_active=1)
+    try:
+        ids = [srv.submit(dev(p.X), dev(p.Q), dev(p.R), dev(p.x0), dev(p.P0), dev(p.Y)) for p in jobs]
+        assert srv.cancel(ids[3]) is True
+        with pytest.raises(kfmeg.KFError) as ei:
+            srv.wait(ids[3])
+        assert ei.value.status == kfmeg.KF_ECANCELED
+        outs = [srv.wait(i) for i in ids[:3]]
+        assert srv.cancel(ids[0]) is False              # already done
+        st = srv.stats()
+        assert st["completed"] == 3 and st["canceled"] == 1
+        xa, _ = alone(jobs[1])
+        assert torch.equal(outs[1][0], xa)
+    finally:
+        srv.close()
