@@ -59,12 +59,12 @@ def kf_update(x_pred: np.ndarray, P_pred: np.ndarray, X: np.ndarray, R: np.ndarr
     return x, P
 
 
-def kf_filter(X, Q, R, x0, P0, Y, keep_cov: bool = True):
-    """Kalman filter for x_t = x_{t-1} + w_t, y_t = X x_t + v_t (eqn1, eqn3 with F = I; eqn6-eqn10).
+def kf_filter(X, Q, R, x0, P0, Y, keep_cov: bool = True, F=None):
+    """Kalman filter for x_t = F x_{t-1} + w_t, y_t = X x_t + v_t (eqn1, eqn3; eqn6-eqn10).
 
-    Returns (xf, Pf, dPf): xf is T x N with xf[t-1] = x_{t|t}; Pf is a T x N x N
-    array of P_{t|t} (None when ``keep_cov`` is false); dPf is T x N with the
-    diagonals of P_{t|t}.
+    F = None is the random walk (F = I) and skips the products with F. Returns
+    (xf, Pf, dPf): xf is T x N with xf[t-1] = x_{t|t}; Pf is a T x N x N array of
+    P_{t|t} (None when ``keep_cov`` is false); dPf is T x N with the diagonals of P_{t|t}.
     """
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
@@ -75,8 +75,12 @@ def kf_filter(X, Q, R, x0, P0, Y, keep_cov: bool = True):
     dPf = np.empty((T, N))
     Pf = np.empty((T, N, N)) if keep_cov else None
     for t in range(T):
-        x_pred = x                                   # eqn6, F = I
-        P_pred = P + Q                               # eqn7
+        if F is None:
+            x_pred = x                               # eqn6, F = I
+            P_pred = P + Q                           # eqn7
+        else:
+            x_pred = F @ x                           # eqn6
+            P_pred = F @ P @ F.T + Q                 # eqn7
         x, P = kf_update(x_pred, P_pred, X, R, Y[t])
         xf[t] = x
         dPf[t] = np.diag(P)
@@ -85,18 +89,22 @@ def kf_filter(X, Q, R, x0, P0, Y, keep_cov: bool = True):
     return xf, Pf, dPf
 
 
-def smoother_gain(P_filt: np.ndarray, Q: np.ndarray) -> np.ndarray:
-    """eqn11: A_t = P_{t|t} P_{t+1|t}^-1 with P_{t+1|t} = P_{t|t} + Q, via a Cholesky solve."""
-    P_next_pred = P_filt + Q
+def smoother_gain(P_filt: np.ndarray, Q: np.ndarray, F=None) -> np.ndarray:
+    """eqn11: A_t = P_{t|t} F^T P_{t+1|t}^-1 with P_{t+1|t} = F P_{t|t} F^T + Q, via a Cholesky solve."""
+    if F is None:
+        P_next_pred = P_filt + Q
+        c = _chol(P_next_pred)
+        return sla.cho_solve(c, P_filt).T            # (P_{t+1|t}^-1 P_{t|t})^T
+    P_next_pred = F @ P_filt @ F.T + Q
     c = _chol(P_next_pred)
-    return sla.cho_solve(c, P_filt).T                # (P_{t+1|t}^-1 P_{t|t})^T
+    return sla.cho_solve(c, F @ P_filt).T            # (P_{t+1|t}^-1 F P_{t|t})^T
 
 
-def rts_smooth(xf: np.ndarray, Pf: np.ndarray, Q: np.ndarray):
+def rts_smooth(xf: np.ndarray, Pf: np.ndarray, Q: np.ndarray, F=None):
     """Fixed-interval smoother (eqn11-eqn13 in the standard RTS reading), t = T-1 .. 1.
 
     Starts from x_{T|T}, P_{T|T} of the filter. Returns (xs, Ps, dPs) shaped like
-    the filter's outputs.
+    the filter's outputs. F = None is the random walk.
     """
     T, N = xf.shape
     xs = np.empty((T, N))
@@ -106,9 +114,13 @@ def rts_smooth(xf: np.ndarray, Pf: np.ndarray, Q: np.ndarray):
     Ps[T - 1] = Pf[T - 1]
     dPs[T - 1] = np.diag(Pf[T - 1])
     for t in range(T - 2, -1, -1):
-        A = smoother_gain(Pf[t], Q)                              # eqn11
-        x_next_pred = xf[t]                                      # eqn6, F = I
-        P_next_pred = Pf[t] + Q                                  # eqn7
+        A = smoother_gain(Pf[t], Q, F)                           # eqn11
+        if F is None:
+            x_next_pred = xf[t]                                  # eqn6, F = I
+            P_next_pred = Pf[t] + Q                              # eqn7
+        else:
+            x_next_pred = F @ xf[t]                              # eqn6
+            P_next_pred = F @ Pf[t] @ F.T + Q                    # eqn7
         xs[t] = xf[t] + A @ (xs[t + 1] - x_next_pred)            # eqn12 (RTS reading)
         Pst = Pf[t] + A @ (Ps[t + 1] - P_next_pred) @ A.T        # eqn13 (RTS reading)
         Ps[t] = (Pst + Pst.T) / 2.0
@@ -163,32 +175,35 @@ def init_from_mne(X, C, R, Y, reg: float = 0.0):
     return J[0].copy(), Q
 
 
-def bf_smooth_means(X, Q, R, x0, P0, Y):
+def bf_smooth_means(X, Q, R, x0, P0, Y, F=None):
     """Smoothed means only, by the backward information recursion (modified Bryson-Frazier).
 
     Not in the paper: an alternative to eqn12 that reaches the same x_{t|T} without the
     smoother gain A_t, so without inverting P_{t+1|t}. With lambda_{T+1} = 0 and, going back,
-        x_{t|T}  = x_{t|t} + P_{t|t} lambda_{t+1}
-        lambda_t = X^T S_t^-1 e_t + (I - K_t X)^T lambda_{t+1}
+        x_{t|T}  = x_{t|t} + P_{t|t} F^T lambda_{t+1}
+        lambda_t = X^T S_t^-1 e_t + (I - K_t X)^T F^T lambda_{t+1}
     where e_t = y_t - X x_{t|t-1}, S_t and K_t are the innovation, its covariance and the
-    gain of eqn8 at step t. (Substituting A_t P_{t+1|t} = P_{t|t} into eqn12 gives the first
-    line; the second follows from P_{t|t} = (I - K_t X) P_{t|t-1}.) The forward pass is the
-    filter above, written out again so that e_t, S_t and K_t are at hand. Returns (T, N).
+    gain of eqn8 at step t. (Substituting A_t P_{t+1|t} = P_{t|t} F^T into eqn12 gives the
+    first line; the second follows from P_{t|t} = (I - K_t X) P_{t|t-1}.) The forward pass
+    is the filter above, written out again so that e_t, S_t and K_t are at hand. F = None is
+    the random walk. Returns (T, N).
     """
     X = np.asarray(X, dtype=np.float64)
     T = Y.shape[0]
     N = X.shape[1]
+    Fm = np.eye(N) if F is None else np.asarray(F, dtype=np.float64)
     x = np.asarray(x0, dtype=np.float64).copy()
     P = np.asarray(P0, dtype=np.float64).copy()
     xf = np.empty((T, N))
     Pf, e, Sf, K = [], [], [], []
     for t in range(T):
-        P_pred = P + Q                                 # eqn7
+        x_pred = Fm @ x                                # eqn6
+        P_pred = Fm @ P @ Fm.T + Q                     # eqn7
         S = X @ P_pred @ X.T + R                       # bracket of eqn8
         cS = _chol(S)
         Kt = sla.cho_solve(cS, X @ P_pred).T           # eqn8
-        et = Y[t] - X @ x                              # innovation of eqn10
-        x = x + Kt @ et                                # eqn10
+        et = Y[t] - X @ x_pred                         # innovation of eqn10
+        x = x_pred + Kt @ et                           # eqn10
         P = P_pred - Kt @ X @ P_pred
         P = (P + P.T) / 2.0
         xf[t] = x
@@ -199,6 +214,7 @@ def bf_smooth_means(X, Q, R, x0, P0, Y):
     xs = np.empty((T, N))
     lam = np.zeros(N)
     for t in range(T - 1, -1, -1):
-        xs[t] = xf[t] + Pf[t] @ lam
-        lam = X.T @ sla.cho_solve(Sf[t], e[t]) + (np.eye(N) - K[t] @ X).T @ lam
+        mu = Fm.T @ lam
+        xs[t] = xf[t] + Pf[t] @ mu
+        lam = X.T @ sla.cho_solve(Sf[t], e[t]) + (np.eye(N) - K[t] @ X).T @ mu
     return xs

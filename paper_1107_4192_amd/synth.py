@@ -31,6 +31,13 @@ Recipes (the sizes and distributions of the five workloads):
   K; each patch has one seeded orientation.
 * ``serving``: a seeded stream of jobs with Poisson arrivals, each built like
   ``paper`` at its own N, m and T.
+* ``neighbourhood``: the ``paper`` workload with the first-order neighbourhood
+  model of eqn2 as the transition F of eqn3: each source keeps (1 - beta) of its
+  own previous value and takes beta/6 of each of its six nearest sources
+  (beta = 0.5). Reading: eqn2 as printed adds the neighbour mean to the full
+  previous value, which makes F's spectral radius about 2 (an exploding
+  process); its mask weights are read as this normalisation, so that F is row
+  stochastic (a stable averaging process; F = I at beta = 0).
 """
 from __future__ import annotations
 
@@ -58,6 +65,10 @@ class Problem:
     Y: np.ndarray          # T x m data
     truth: np.ndarray | None = None   # T x N simulated sources (not used by the path)
     meta: dict = field(default_factory=dict)
+    F: tuple | None = None            # transition of eqn3 as CSR (row_ptr, col_idx, val); None = identity
+
+    def F_dense(self) -> np.ndarray | None:
+        return None if self.F is None else csr_to_dense(*self.F, self.N)
 
     @property
     def N(self) -> int:
@@ -250,3 +261,78 @@ def serving_jobs(seed: int = 5, n_jobs: int = 64, rate_per_s: float = 4.0,
             "seed": int(seed * 1000 + j),
         })
     return jobs
+
+
+def neighbourhood_transition(points: np.ndarray, k: int = 6, beta: float = 0.5, chunk: int = 1024):
+    """CSR (row_ptr int32, col_idx int32, val float64) of F = (1 - beta) I + beta/k A_k, where row p of
+    A_k has ones at the k sources nearest to source p (eqn2 with its mask read as a normalisation)."""
+    n = points.shape[0]
+    nbr = np.empty((n, k), dtype=np.int64)
+    sq = (points ** 2).sum(axis=1)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        d2 = sq[a:b, None] + sq[None, :] - 2.0 * points[a:b] @ points.T
+        d2[np.arange(b - a), np.arange(a, b)] = np.inf          # not its own neighbour
+        idx = np.argpartition(d2, k, axis=1)[:, :k]
+        nbr[a:b] = np.sort(idx, axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    cols, vals = [], []
+    for p in range(n):
+        entries = {p: 1.0 - beta}
+        for q in nbr[p]:
+            entries[int(q)] = entries.get(int(q), 0.0) + beta / k
+        cs = sorted(entries)
+        cols.extend(cs)
+        vals.extend(entries[c] for c in cs)
+        row_ptr[p + 1] = len(cols)
+    return row_ptr, np.asarray(cols, dtype=np.int32), np.asarray(vals, dtype=np.float64)
+
+
+def dense_to_csr(F: np.ndarray):
+    """CSR of a dense matrix (explicit zeros dropped)."""
+    n = F.shape[0]
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    cols, vals = [], []
+    for i in range(n):
+        nz = np.nonzero(F[i])[0]
+        cols.extend(nz.tolist())
+        vals.extend(F[i, nz].tolist())
+        row_ptr[i + 1] = len(cols)
+    return row_ptr, np.asarray(cols, dtype=np.int32), np.asarray(vals, dtype=np.float64)
+
+
+def csr_to_dense(row_ptr, col_idx, val, n: int) -> np.ndarray:
+    F = np.zeros((n, n))
+    for i in range(n):
+        for e in range(row_ptr[i], row_ptr[i + 1]):
+            F[i, col_idx[e]] += val[e]
+    return F
+
+
+def neighbourhood(seed: int = 2, N: int = 5124, m: int = 306, T: int = 200, beta: float = 0.5,
+                  snr_db: float = 5.0) -> Problem:
+    """``paper`` workload with the six-neighbour transition of eqn2 (see the module notes)."""
+    p = paper(seed=seed, N=N, m=m, T=T, snr_db=snr_db)
+    g_src = _rngs(seed, 5)[0]
+    sites = _shell(g_src, N)                     # the same draw as in ``paper``
+    p.F = neighbourhood_transition(sites, 6, beta)
+    p.name = f"neighbourhood_N{N}_m{m}_T{T}"
+    p.meta["beta"] = beta
+    return p
+
+
+def small_random_F(seed: int, N: int, m: int, T: int, density: float = 1.0, radius: float = 0.9) -> Problem:
+    """``small_random`` with a random transition F (spectral radius ``radius``; a fraction
+    ``density`` of off-diagonal entries kept)."""
+    p = small_random(seed, N, m, T)
+    g = _rngs(seed + 1000, 2)
+    F = g[0].normal(size=(N, N))
+    if density < 1.0:
+        keep = g[1].random(size=(N, N)) < density
+        np.fill_diagonal(keep, True)
+        F = F * keep
+    rho = max(abs(np.linalg.eigvals(F))) if N > 0 else 1.0
+    F = F * (radius / rho)
+    p.F = dense_to_csr(F)
+    p.name = f"smallF_N{N}_m{m}_T{T}"
+    return p

@@ -376,3 +376,69 @@ def test_bf_pin_catches_planted_transpose():
     p = synth.small_random(17, 5, 3, 6)
     bf = oracle.joint_posterior(p.X, p.Q, p.R, p.x0, p.P0, p.Y)
     assert rel(_bf_transposed(p.X, p.Q, p.R, p.x0, p.P0, p.Y), bf[2]) > 1e-6
+
+
+# ---------------------------------------------------------------- a transition F (eqn3)
+@pytest.mark.parametrize("seed,N,m,T,density", [(21, 3, 2, 4, 1.0), (22, 5, 3, 6, 1.0), (23, 8, 4, 5, 0.4),
+                                                (24, 12, 5, 6, 0.3)])
+def test_transition_brute_force(seed, N, m, T, density):
+    p = synth.small_random_F(seed, N, m, T, density)
+    F = p.F_dense()
+    xf, Pf, _ = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=F)
+    xs, Ps, _ = oracle.rts_smooth(xf, Pf, p.Q, F=F)
+    bf = oracle.joint_posterior(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=F)
+    for got, want in zip((xf, Pf, xs, Ps), bf):
+        assert rel(got, want) < 1e-10
+    assert rel(oracle.bf_smooth_means(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=F), bf[2]) < 1e-10
+    bi = oracle.joint_posterior_information(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=F)
+    assert rel(bi[2], bf[2]) < 1e-9
+
+
+def test_transition_prior_is_lyapunov_recursion():
+    p = synth.small_random_F(25, 4, 2, 5)
+    F, T, N = p.F_dense(), 5, 4
+    from oracle.joint import joint_prior
+    mu, Sig = joint_prior(p.Q, p.x0, p.P0, T, F)
+    C, x = p.P0.copy(), p.x0.copy()
+    for t in range(T):
+        C = F @ C @ F.T + p.Q                  # Cov(x_t, x_t) by the one-step recursion
+        x = F @ x
+        blk = slice(t * N, (t + 1) * N)
+        assert rel(Sig[blk, blk], C) < 1e-13 and rel(mu[blk], x) < 1e-13
+        if t + 1 < T:                          # Cov(x_{t+1}, x_t) = F Cov(x_t, x_t)
+            assert rel(Sig[(t + 1) * N:(t + 2) * N, blk], F @ C) < 1e-13
+
+
+def test_identity_transition_reproduces_random_walk():
+    p = synth.small_random(26, 6, 3, 5)
+    I = np.eye(6)
+    a = run(p)
+    xf, Pf, _ = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=I)
+    xs, Ps, _ = oracle.rts_smooth(xf, Pf, p.Q, F=I)
+    assert rel(xf, a[0]) < 1e-14 and rel(xs, a[3]) < 1e-14 and rel(Ps, a[4]) < 1e-14
+
+
+def test_neighbourhood_transition_is_row_stochastic_six_neighbours():
+    pts = np.random.default_rng(3).normal(size=(200, 3))
+    rp, ci, v = synth.neighbourhood_transition(pts, 6, 0.5)
+    F = synth.csr_to_dense(rp, ci, v, 200)
+    assert np.allclose(F.sum(axis=1), 1.0, rtol=0, atol=1e-15)
+    assert np.all(np.diff(rp) == 7) and np.allclose(np.diag(F), 0.5)
+    d = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d, np.inf)
+    for i in (0, 17, 199):
+        assert set(np.nonzero(F[i])[0]) - {i} == set(np.argsort(d[i])[:6])
+
+
+def test_transition_pin_catches_missing_ft_in_gain():
+    p = synth.small_random_F(27, 5, 3, 5)
+    F = p.F_dense()
+    bf = oracle.joint_posterior(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=F)
+    xf, Pf, _ = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=F)
+    T = xf.shape[0]
+    xs = xf.copy()
+    for t in range(T - 2, -1, -1):              # planted: A_t = P_t P_{t+1|t}^-1 (F^T dropped)
+        Pn = F @ Pf[t] @ F.T + p.Q
+        A = np.linalg.solve(Pn, Pf[t]).T
+        xs[t] = xf[t] + A @ (xs[t + 1] - F @ xf[t])
+    assert rel(xs, bf[2]) > 1e-6
