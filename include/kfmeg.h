@@ -145,6 +145,22 @@ kf_status kf_smooth_batch(kf_plan* plan, int64_t B, double* x_smooth,
 kf_status kf_smooth_means(kf_plan* plan, double* x_smooth);
 kf_status kf_smooth_means_batch(kf_plan* plan, int64_t B, double* x_smooth);
 
+/*
+ * kf_set_transition: use x_t = F x_{t-1} + w_t (eqn3) instead of the random
+ * walk, with F (N x N) sparse in CSR form: row_ptr (N+1 int32, from 0 to nnz),
+ * col_idx (nnz int32, in [0, N)), val (nnz float64), all device pointers, copied
+ * into the plan (the caller may free them afterwards). The six-neighbour model
+ * of eqn2 is such an F with seven entries per row. The filter then predicts
+ * x_{t|t-1} = F x_{t-1|t-1}, P_{t|t-1} = F P_{t-1|t-1} F^T + Q (eqn6, eqn7),
+ * and the smoother uses A_t = P_{t|t} F^T P_{t+1|t}^-1 (eqn11) and
+ * x_{t+1|t} = F x_{t|t} in eqn12; kf_smooth_means applies F^T to lambda.
+ * nnz = 0 with null pointers restores F = I. Adds 2 N^2 float64 of workspace;
+ * invalidates the last filter call. Not available on serving plans. Returns
+ * KF_EINVAL for a malformed matrix.
+ */
+kf_status kf_set_transition(kf_plan* plan, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                            const double* val);
+
 /* Copy the stored filtered covariance P_{t|t} (1 <= t <= T) into P_out (N x N, device). */
 kf_status kf_get_filtered_cov(kf_plan* plan, int64_t t, double* P_out);
 

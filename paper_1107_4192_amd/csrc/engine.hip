@@ -92,6 +92,12 @@ struct kf_plan {
     double *fac_C = nullptr, *fac_L = nullptr, *fac_w = nullptr;
     int64_t wcap = 0;
     std::vector<double*> bfac_w;            // per-data-set factor buffers grown past one data set
+    // transition matrix F of eqn3 (CSR on the device) and its transpose; absent: F = I
+    bool hasF = false;
+    Csr F, Ft;
+    std::vector<void*> fallocs;
+    double *Fg = nullptr, *Fp = nullptr, *xp = nullptr;   // P F^T, F P F^T + Q, F x
+    double* Ub = nullptr;                   // B x ldN: F applied to B means
     std::string err;
     // profiling of the smoother's N x N x N products (event pairs around each launch)
     bool prof = false;
@@ -247,17 +253,24 @@ kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* 
                           float* Pout32, double* diag_out, const double* y, double* x_out_row) {
     const int N = (int)p->N, m = (int)p->m;
     hipStream_t s = p->stream;
-    // B = X (P_prev + Q) = X P_prev + X Q, in float64 in both precisions: the gain and the
+    // P_pred = P_prev + Q (F = I, never formed) or F P_prev F^T + Q (formed as F (P_prev F^T) + Q)
+    const double* Ppred = nullptr;
+    if (p->hasF) {
+        HIPCK(dense_sparse_t(p->F, Pprev64, p->ldN, p->Fg, p->ldN, s));
+        HIPCK(spmm_rows(p->F, p->Fg, p->ldN, 1.0, p->Q, p->ldN, 1.0, nullptr, 0, 0.0, p->Fp, false, p->ldN, s));
+        Ppred = p->Fp;
+    }
+    // B = X P_pred: with F = I, X P_prev + X Q. Float64 in both precisions: the gain and the
     // mean depend on it through S^{-1}, where rounding is amplified by cond(S).
     {
         GemmProblem g;
         g.M = m; g.N = N; g.K = N;
         g.ksplit = 4;
         g.partial = p->partial;
-        g.Cin = p->XQ; g.ldcin = p->ldN; g.beta = 1.0;
+        if (!Ppred) { g.Cin = p->XQ; g.ldcin = p->ldN; g.beta = 1.0; }
         g.C = p->Bm; g.ldc = p->ldN;
         g.A = p->X; g.lda = p->ldN;
-        g.B = Pprev64; g.ldb = p->ldN; g.flags = G_TB;   // P symmetric: read row-contiguous
+        g.B = Ppred ? Ppred : Pprev64; g.ldb = p->ldN; g.flags = G_TB;   // P symmetric: read row-contiguous
         HIPCK(gemm1(Dt::F64, g, s));
     }
     // S = B X^T + R
@@ -284,9 +297,14 @@ kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* 
         HIPCK(gemm1(Dt::F64, g, s));
     }
     if (y) {
-        HIPCK(resid(p->X, p->ldN, p->xw, y, p->e, m, N, s));
+        const double* xpred = p->xw;                                     // eqn6
+        if (p->hasF) {
+            HIPCK(spmv_rows(p->F, p->xw, p->ldN, 1, p->xp, p->ldN, s));
+            xpred = p->xp;
+        }
+        HIPCK(resid(p->X, p->ldN, xpred, y, p->e, m, N, s));
         HIPCK(trmv_lower(p->Lis, p->ldm, p->e, p->w, m, s));
-        HIPCK(gemv_t_add(p->Cm, p->ldN, p->w, p->xw, p->xw, x_out_row, m, N, s));
+        HIPCK(gemv_t_add(p->Cm, p->ldN, p->w, xpred, p->xw, x_out_row, m, N, s));
     }
     // P_t = P_prev + Q - C^T C
     {
@@ -294,8 +312,8 @@ kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* 
         g.M = N; g.N = N; g.K = m;
         g.flags = G_TA | G_LOWER | G_MIRROR;
         g.alpha = -1.0;
-        g.Cin = Pprev64; g.ldcin = p->ldN; g.beta = 1.0;
-        g.Cin2 = p->Q; g.ldcin2 = p->ldN; g.gamma = 1.0;
+        g.Cin = Ppred ? Ppred : Pprev64; g.ldcin = p->ldN; g.beta = 1.0;
+        if (!Ppred) { g.Cin2 = p->Q; g.ldcin2 = p->ldN; g.gamma = 1.0; }
         g.C = Pout64; g.ldc = p->ldN;
         g.C32 = Pout32; g.ldc32 = p->ldN;
         g.diag = diag_out;
@@ -317,13 +335,14 @@ kf_status ensure_batch(kf_plan* p, int64_t B) {
         p->err = "several data sets per call are not available on a serving plan";
         return KF_EINVAL;
     }
-    for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb})
+    for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb, p->Ub})
         if (b) (void)hipFree(b);
-    p->Eb = p->Wb = p->Xb0 = p->Vb = nullptr;
+    p->Eb = p->Wb = p->Xb0 = p->Vb = p->Ub = nullptr;
     p->bcap = 0;
     const size_t bm = (size_t)B * p->ldm * 8, bn = (size_t)B * p->ldN * 8;
     if (hipMalloc(&p->Eb, bm) != hipSuccess || hipMalloc(&p->Wb, bm) != hipSuccess ||
-        hipMalloc(&p->Xb0, bn) != hipSuccess || hipMalloc(&p->Vb, bn) != hipSuccess) {
+        hipMalloc(&p->Xb0, bn) != hipSuccess || hipMalloc(&p->Vb, bn) != hipSuccess ||
+        hipMalloc(&p->Ub, bn) != hipSuccess) {
         (void)hipGetLastError();
         p->err = "device allocation for " + std::to_string(B) + " data sets failed";
         return KF_ENOMEM;
@@ -346,6 +365,11 @@ kf_status filter_mean_batch(kf_plan* p, int64_t B, const double* Xprev, int64_t 
                             int64_t ldy, double* Xt, int64_t ldx) {
     hipStream_t s = p->stream;
     const int N = (int)p->N, m = (int)p->m;
+    if (p->hasF) {                           // predicted means F x (eqn6)
+        HIPCK(spmv_rows(p->F, Xprev, ldprev, (int)B, p->Ub, p->ldN, s));
+        Xprev = p->Ub;
+        ldprev = p->ldN;
+    }
     {
         GemmProblem g;                       // E = Y_t - X_prev X^T
         g.M = (int)B; g.N = m; g.K = N;
@@ -384,8 +408,15 @@ kf_status smooth_mean_batch(kf_plan* p, int64_t B, const double* A, int64_t t, c
     hipStream_t s = p->stream;
     const int N = (int)p->N;
     const int64_t ldx = p->T_done * N;
-    HIPCK(axpby3((int)B, N, p->Vb, false, p->ldN, xs + (t + 1) * N, false, ldx, xf + t * N, false, ldx, -1.0,
-                 nullptr, false, 0, 0.0, s));
+    const double* xpred = xf + t * N;        // x_{t+1|t} rows: F x_{t|t}, or x_{t|t} with F = I
+    int64_t ldp = ldx;
+    if (p->hasF) {
+        HIPCK(spmv_rows(p->F, xf + t * N, ldx, (int)B, p->Ub, p->ldN, s));
+        xpred = p->Ub;
+        ldp = p->ldN;
+    }
+    HIPCK(axpby3((int)B, N, p->Vb, false, p->ldN, xs + (t + 1) * N, false, ldx, xpred, false, ldp, -1.0, nullptr,
+                 false, 0, 0.0, s));
     GemmProblem g;
     g.M = (int)B; g.N = N; g.K = N;
     g.A = p->Vb; g.lda = p->ldN;
@@ -779,8 +810,15 @@ kf_status gain_batch(kf_plan* p, int set, int count, const int64_t* ts, const vo
             HIPCK(copy2d_r32(N, N, p->Pt64[set][b], ld, Pt[b], is32[b], ld, s));
             P64[b] = p->Pt64[set][b];
         }
-        // W = P_t + Q  (= P_{t+1|t}, eqn7)
-        HIPCK(axpby3(N, N, p->W[b], false, ld, P64[b], false, ld, p->Q, false, ld, 1.0, nullptr, false, 0, 0.0, s));
+        if (p->hasF) {
+            // G_t = P_t F^T (kept in A_t's buffer until A_t overwrites it); W = F G_t + Q (eqn7)
+            HIPCK(dense_sparse_t(p->F, P64[b], ld, p->Ab[set][b], ld, s));
+            HIPCK(spmm_rows(p->F, p->Ab[set][b], ld, 1.0, p->Q, ld, 1.0, nullptr, 0, 0.0, p->W[b], false, ld, s));
+        } else {
+            // W = P_t + Q  (= P_{t+1|t}, eqn7)
+            HIPCK(axpby3(N, N, p->W[b], false, ld, P64[b], false, ld, p->Q, false, ld, 1.0, nullptr, false, 0, 0.0,
+                         s));
+        }
         steps[b] = (int)ts[b] + 1;
     }
     HIPCK(chol_inv_batch(N, p->W, ld, p->Li, ld, count, p->dstatus, W_PPRED, steps, s));
@@ -788,8 +826,8 @@ kf_status gain_batch(kf_plan* p, int set, int count, const int64_t* ts, const vo
     // transposed in place so that both products read their second operand row-contiguous.
     GemmProblem g[kMaxBatch], h[kMaxBatch];
     for (int b = 0; b < count; ++b) {
-        g[b].M = N; g[b].N = N; g[b].K = N;    // H = P_t Li^T   (B(l,k) = Li[k][l], zero for l > k)
-        g[b].A = P64[b]; g[b].lda = ld;
+        g[b].M = N; g[b].N = N; g[b].K = N;    // H = P_t F^T Li^T   (B(l,k) = Li[k][l], zero for l > k)
+        g[b].A = p->hasF ? p->Ab[set][b] : P64[b]; g[b].lda = ld;
         g[b].B = p->Li[b]; g[b].ldb = ld; g[b].flags = G_TB | G_BUPPER;
         g[b].C = p->W[b]; g[b].ldc = ld;
         h[b].M = N; h[b].N = N; h[b].K = N;    // A_t = H Li     (B(k,j) = Li[k][j] = LiT[j][k])
@@ -814,11 +852,23 @@ kf_status chain_step(kf_plan* p, int set, int b, int64_t t, const void* Pt, cons
     const double* Pt64 = p->store32 ? p->Pt64[set][b] : static_cast<const double*>(Pt);
     const double* A = p->Ab[set][b];
     // x_{t|T} = x_{t|t} + A_t (x_{t+1|T} - x_{t|t})   (eqn12, RTS reading)
-    if (p->B_done == 1) HIPCK(gemv_smooth(A, ld, xf + t * N, xs + (t + 1) * N, xs + t * N, N, s));
+    if (p->B_done == 1) {
+        const double* xpred = xf + t * N;    // x_{t+1|t} = F x_{t|t} (eqn6)
+        if (p->hasF) {
+            HIPCK(spmv_rows(p->F, xf + t * N, N, 1, p->xp, N, s));
+            xpred = p->xp;
+        }
+        HIPCK(gemv_smooth(A, ld, xf + t * N, xpred, xs + (t + 1) * N, xs + t * N, N, s));
+    }
     else TRY(smooth_mean_batch(p, p->B_done, A, t, xf, xs));
     if (mixed(p)) {
         // D = P_{t+1|T} - P_t - Q in float32; M = A D; P_{t|T} = P_t + M A^T   (eqn13)
-        HIPCK(axpby3(N, N, p->D32, true, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
+        if (p->hasF) {                      // D = P_{t+1|T} - F (P_t F^T) - Q
+            HIPCK(dense_sparse_t(p->F, Pt64, ld, p->Fg, ld, s));
+            HIPCK(spmm_rows(p->F, p->Fg, ld, -1.0, Ps_next, ld, 1.0, p->Q, ld, -1.0, p->D32, true, ld, s));
+        } else {
+            HIPCK(axpby3(N, N, p->D32, true, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
+        }
         GemmProblem g;
         g.M = N; g.N = N; g.K = N;
         g.A = p->A32[set][b]; g.lda = ld; g.B = p->D32; g.ldb = ld; g.flags = G_TB;   // D symmetric
@@ -832,7 +882,12 @@ kf_status chain_step(kf_plan* p, int set, int b, int64_t t, const void* Pt, cons
         TRY(big_gemm(p, Dt::F32, h, (double)N * N * N, s, &p->ts_low));
     } else {
         // D = P_{t+1|T} - P_t - Q;  M = A_t D;  P_{t|T} = P_t + M A_t^T   (eqn13)
-        HIPCK(axpby3(N, N, p->Dm, false, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
+        if (p->hasF) {                      // D = P_{t+1|T} - F (P_t F^T) - Q   (M's buffer holds P_t F^T)
+            HIPCK(dense_sparse_t(p->F, Pt64, ld, p->Mm, ld, s));
+            HIPCK(spmm_rows(p->F, p->Mm, ld, -1.0, Ps_next, ld, 1.0, p->Q, ld, -1.0, p->Dm, false, ld, s));
+        } else {
+            HIPCK(axpby3(N, N, p->Dm, false, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
+        }
         GemmProblem g;
         g.M = N; g.N = N; g.K = N;
         g.A = A; g.lda = ld;
@@ -954,8 +1009,8 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
 }
 
 // Smoothed means alone for the B data sets of the last filter call (backward information
-// recursion): x_{t|T} = x_{t|t} + P_{t|t} lambda_{t+1},
-// lambda_t = lambda_{t+1} + X^T L_t^-T (L_t^-1 e_t - C_t lambda_{t+1}), lambda_T = 0 (0-based t).
+// recursion): with mu = F^T lambda_{t+1} (lambda_{t+1} itself when F = I),
+// x_{t|T} = x_{t|t} + P_{t|t} mu, lambda_t = mu + X^T L_t^-T (L_t^-1 e_t - C_t mu), lambda_T = 0.
 kf_status smooth_means_impl(kf_plan* p, int64_t B, double* xs) {
     hipStream_t s = p->stream;
     const int64_t T = p->T_done, N = p->N, m = p->m;
@@ -971,6 +1026,11 @@ kf_status smooth_means_impl(kf_plan* p, int64_t B, double* xs) {
     for (int64_t t = T - 1; t >= 0; --t) {
         const double* ln = lam[(t + 1) & 1];       // lambda_{t+1}
         double* lc = lam[t & 1];                   // lambda_t
+        if (p->hasF) {                             // everything below uses F^T lambda_{t+1}
+            double* mu = B == 1 ? p->xp : p->Ub;
+            HIPCK(spmv_rows(p->Ft, ln, ld, (int)B, mu, ld, s));
+            ln = mu;
+        }
         if (t < T - 1) {
             // P_{t|t}: a stored slot, or recomputed from the checkpoint before it
             const void* Pt;
@@ -1092,6 +1152,80 @@ kf_status kf_smooth_means_batch(kf_plan* p, int64_t B, double* x_smooth) {
 
 kf_status kf_smooth_means(kf_plan* p, double* x_smooth) { return kf_smooth_means_batch(p, 1, x_smooth); }
 
+kf_status kf_set_transition(kf_plan* p, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                            const double* val) {
+    if (!p) return KF_EINVAL;
+    p->err.clear();
+    const int64_t N = p->N;
+    p->T_done = 0;                                  // a new model: the last filter call no longer applies
+    if (nnz == 0 && !row_ptr && !col_idx && !val) {
+        p->hasF = false;
+        return KF_OK;
+    }
+    if (p->arena) {
+        p->err = "kf_set_transition: not available on a serving plan";
+        return KF_EINVAL;
+    }
+    if (nnz <= 0 || nnz > ((int64_t)1 << 31) - 1 || !row_ptr || !col_idx || !val) {
+        p->err = "kf_set_transition: need 0 < nnz < 2^31 and non-null row_ptr, col_idx, val";
+        return KF_EINVAL;
+    }
+    // Validate on the host: row_ptr non-decreasing from 0 to nnz, column indices in range.
+    std::vector<int32_t> rp(N + 1), ci(nnz);
+    std::vector<double> v(nnz);
+    HIPCK(hipMemcpy(rp.data(), row_ptr, (N + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCK(hipMemcpy(ci.data(), col_idx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCK(hipMemcpy(v.data(), val, nnz * sizeof(double), hipMemcpyDeviceToHost));
+    bool ok = rp[0] == 0 && rp[N] == nnz;
+    for (int64_t i = 0; ok && i < N; ++i) ok = rp[i] <= rp[i + 1];
+    for (int64_t e = 0; ok && e < nnz; ++e) ok = ci[e] >= 0 && ci[e] < N && std::isfinite(v[e]);
+    if (!ok) {
+        p->err = "kf_set_transition: row_ptr must rise from 0 to nnz, col_idx lie in [0, N), values be finite";
+        return KF_EINVAL;
+    }
+    // The transpose (for F^T in the mean-only smoother), by a counting sort on the host.
+    std::vector<int32_t> trp(N + 1, 0), tci(nnz);
+    std::vector<double> tv(nnz);
+    for (int64_t e = 0; e < nnz; ++e) ++trp[ci[e] + 1];
+    for (int64_t i = 0; i < N; ++i) trp[i + 1] += trp[i];
+    std::vector<int32_t> fill(trp.begin(), trp.end() - 1);
+    for (int64_t i = 0; i < N; ++i)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int32_t d = fill[ci[e]]++;
+            tci[d] = (int32_t)i;
+            tv[d] = v[e];
+        }
+    for (void* a : p->fallocs) (void)hipFree(a);
+    p->fallocs.clear();
+    p->hasF = false;
+    auto dev = [&](const void* src, size_t bytes) -> void* {
+        void* d = nullptr;
+        if (hipMalloc(&d, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        p->fallocs.push_back(d);
+        if (src && hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+        return d;
+    };
+    const size_t NN = (size_t)N * p->ldN * 8;
+    void *a = dev(rp.data(), (N + 1) * 4), *b = dev(ci.data(), nnz * 4), *c = dev(v.data(), nnz * 8);
+    void *d = dev(trp.data(), (N + 1) * 4), *e = dev(tci.data(), nnz * 4), *f = dev(tv.data(), nnz * 8);
+    void *g = dev(nullptr, NN), *h = dev(nullptr, NN), *x = dev(nullptr, (size_t)p->ldN * 8);
+    if (!a || !b || !c || !d || !e || !f || !g || !h || !x) {
+        p->err = "kf_set_transition: device allocation failed";
+        return KF_ENOMEM;
+    }
+    p->F.n = p->Ft.n = (int)N;
+    p->F.rp = static_cast<int*>(a); p->F.ci = static_cast<int*>(b); p->F.v = static_cast<double*>(c);
+    p->Ft.rp = static_cast<int*>(d); p->Ft.ci = static_cast<int*>(e); p->Ft.v = static_cast<double*>(f);
+    p->Fg = static_cast<double*>(g);
+    p->Fp = static_cast<double*>(h);
+    p->xp = static_cast<double*>(x);
+    p->hasF = true;
+    return KF_OK;
+}
+
 kf_status kf_get_filtered_cov(kf_plan* p, int64_t t, double* P_out) {
     if (!p) return KF_EINVAL;
     p->err.clear();
@@ -1149,9 +1283,10 @@ void kf_destroy(kf_plan* p) {
     for (hipEvent_t e : {p->ev_start, p->ev_gain[0], p->ev_gain[1], p->ev_chain[0], p->ev_chain[1]})
         if (e) (void)hipEventDestroy(e);
     if (p->s2) (void)hipStreamDestroy(p->s2);
-    for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb})
+    for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb, p->Ub})
         if (b) (void)hipFree(b);
     for (double* b : p->bfac_w) (void)hipFree(b);
+    for (void* a : p->fallocs) (void)hipFree(a);
     for (void* a : p->allocs) {
         if (p->arena) p->arena->release(a);
         else (void)hipFree(a);

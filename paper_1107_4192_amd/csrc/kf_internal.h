@@ -90,8 +90,8 @@ hipError_t trmv_lower(const double* L, int64_t ldl, const double* e, double* w, 
 // x_out = x_in + C^T w  (C: m x N, ld ldc); optional copy to x_copy
 hipError_t gemv_t_add(const double* C, int64_t ldc, const double* w, const double* x_in,
                       double* x_out, double* x_copy, int m, int N, hipStream_t s);
-// out = x + A (v - x)   (A: N x N, ld lda)   -- smoothed mean (eqn12)
-hipError_t gemv_smooth(const double* A, int64_t lda, const double* x, const double* v,
+// out = x + A (v - u)   (A: N x N, ld lda)   -- smoothed mean (eqn12; u = F x, or x when F = I)
+hipError_t gemv_smooth(const double* A, int64_t lda, const double* x, const double* u, const double* v,
                        double* out, int N, hipStream_t s);
 // out = x + P lam  (P: N x N float or double, ld ldp)   -- mean-only smoother
 hipError_t gemv_add(const void* P, bool p32, int64_t ldp, const double* lam, const double* x, double* out, int N,
@@ -121,5 +121,22 @@ hipError_t nonfinite_scan(const double* v, int64_t n, int* flag, hipStream_t s);
 hipError_t transpose_inplace(double* A, int64_t lda, int n, hipStream_t s);
 // store diag of a square double matrix to out
 hipError_t diag_copy(const double* A, int64_t lda, int n, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- sparse transition (eqn3)
+struct Csr {
+    int n = 0;                    // square n x n
+    const int* rp = nullptr;      // row_ptr[n + 1] (device)
+    const int* ci = nullptr;      // col_idx[nnz] (device)
+    const double* v = nullptr;    // values[nnz] (device)
+};
+constexpr size_t kMaxTransitionLds = 64 * 1024;    // one dense row of P staged in LDS for P F^T
+// Y = alpha F A + beta1 C1 + beta2 C2 (A, C1, C2: n x n float64; C1/C2 may be null; Y float or double)
+hipError_t spmm_rows(const Csr& F, const double* A, int64_t lda, double alpha, const double* C1, int64_t ldc1,
+                     double beta1, const double* C2, int64_t ldc2, double beta2, void* Y, bool y32, int64_t ldy,
+                     hipStream_t s);
+// G = P F^T (P, G: n x n float64)
+hipError_t dense_sparse_t(const Csr& F, const double* P, int64_t ldp, double* G, int64_t ldg, hipStream_t s);
+// Y[b] = F X[b] for `rows` vectors (rows of X and Y, leading dimensions ldx, ldy)
+hipError_t spmv_rows(const Csr& F, const double* X, int64_t ldx, int rows, double* Y, int64_t ldy, hipStream_t s);
 
 }  // namespace kfmeg

@@ -69,10 +69,10 @@ __global__ __launch_bounds__(TPB) void gemv_t_add_kernel(const double* C, int64_
     }
 }
 
-// out_i = x_i + sum_k A[i][k] (v_k - x_k); one wave per row, four interleaved partial sums
+// out_i = x_i + sum_k A[i][k] (v_k - u_k); one wave per row, four interleaved partial sums
 // per lane so that four loads are in flight, combined in a fixed order.
-__global__ void gemv_smooth_kernel(const double* A, int64_t lda, const double* x, const double* v, double* out,
-                                   int N) {
+__global__ void gemv_smooth_kernel(const double* A, int64_t lda, const double* x, const double* u, const double* v,
+                                   double* out, int N) {
     const int row = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= N) return;
@@ -80,12 +80,12 @@ __global__ void gemv_smooth_kernel(const double* A, int64_t lda, const double* x
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int k = lane;
     for (; k + 192 < N; k += 256) {
-        s0 += ar[k] * (v[k] - x[k]);
-        s1 += ar[k + 64] * (v[k + 64] - x[k + 64]);
-        s2 += ar[k + 128] * (v[k + 128] - x[k + 128]);
-        s3 += ar[k + 192] * (v[k + 192] - x[k + 192]);
+        s0 += ar[k] * (v[k] - u[k]);
+        s1 += ar[k + 64] * (v[k + 64] - u[k + 64]);
+        s2 += ar[k + 128] * (v[k + 128] - u[k + 128]);
+        s3 += ar[k + 192] * (v[k + 192] - u[k + 192]);
     }
-    for (; k < N; k += 64) s0 += ar[k] * (v[k] - x[k]);
+    for (; k < N; k += 64) s0 += ar[k] * (v[k] - u[k]);
     double s = wave_sum((s0 + s1) + (s2 + s3));
     if (lane == 0) out[row] = x[row] + s;
 }
@@ -268,9 +268,9 @@ hipError_t gemv_t_add(const double* C, int64_t ldc, const double* w, const doubl
     return hipGetLastError();
 }
 
-hipError_t gemv_smooth(const double* A, int64_t lda, const double* x, const double* v, double* out, int N,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(gemv_smooth_kernel, dim3((N + 3) / 4), dim3(TPB), 0, s, A, lda, x, v, out, N);
+hipError_t gemv_smooth(const double* A, int64_t lda, const double* x, const double* u, const double* v, double* out,
+                       int N, hipStream_t s) {
+    hipLaunchKernelGGL(gemv_smooth_kernel, dim3((N + 3) / 4), dim3(TPB), 0, s, A, lda, x, u, v, out, N);
     return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ EXPORTS = ("kf_default_options", "kf_create", "kf_filter", "kf_smooth", "kf_get_
            "mne_solve", "kf_destroy", "kf_last_error", "kf_plan_bytes", "kfd_gemm", "kfd_chol_inv", "kf_set_profiling", "kf_get_profile",
            "kfs_create", "kfs_submit", "kfs_wait", "kfs_job_info", "kfs_get_stats", "kfs_last_error",
            "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch", "kfd_gemm_tail", "kf_smooth_means",
-           "kf_smooth_means_batch", "kfs_cancel")
+           "kf_smooth_means_batch", "kfs_cancel",
+           "kf_set_transition")
 
 
 class KFError(RuntimeError):
@@ -72,6 +73,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_filter.restype = ctypes.c_int
     lib.kf_smooth.argtypes = [vp, dp, dp, dp]
     lib.kf_smooth.restype = ctypes.c_int
+    lib.kf_set_transition.argtypes = [vp, i64, dp, dp, dp]
+    lib.kf_set_transition.restype = ctypes.c_int
     lib.kf_smooth_means.argtypes = [vp, dp]
     lib.kf_smooth_means.restype = ctypes.c_int
     lib.kf_smooth_means_batch.argtypes = [vp, i64, dp]
@@ -215,6 +218,18 @@ def kf_smooth_batch(plan: int, x_smooth, Pdiag_smooth=None, P_smooth=None) -> No
                              _dev(Pdiag_smooth, "Pdiag_smooth", (T, N)) if Pdiag_smooth is not None else None,
                              _dev(P_smooth, "P_smooth", (T, N, N)) if P_smooth is not None else None)
     _check(lib, st, plan)
+
+
+def kf_set_transition(plan: int, F) -> None:
+    """F: None (random walk) or a CSR triple (row_ptr int32, col_idx int32, val float64), numpy or device."""
+    lib = load_library()
+    if F is None:
+        _check(lib, lib.kf_set_transition(plan, 0, None, None, None), plan)
+        return
+    rp, ci, v = (torch.as_tensor(a).to("cuda").contiguous() for a in F)
+    if rp.dtype != torch.int32 or ci.dtype != torch.int32 or v.dtype != torch.float64:
+        raise TypeError("F: row_ptr and col_idx must be int32, val float64")
+    _check(lib, lib.kf_set_transition(plan, int(ci.numel()), rp.data_ptr(), ci.data_ptr(), v.data_ptr()), plan)
 
 
 def kf_smooth_means(plan: int, x_smooth) -> None:
@@ -414,11 +429,17 @@ class KalmanSmoother:
 
     def __init__(self, X, Q, R, x0, P0, T_max: int, precision: int = KF_FP64, store_fp32: bool = False,
                  hbm_budget_bytes: int = 0, checkpoint_stride: int = 0, keep_gain_factors: bool = False,
-                 stream=None):
+                 F=None, stream=None):
         self.m, self.N = X.shape
         self.T_max = T_max
         self.opt = options(precision, store_fp32, hbm_budget_bytes, checkpoint_stride, keep_gain_factors)
         self.plan = kf_create(self.N, self.m, T_max, X, Q, R, x0, P0, self.opt, stream)
+        if F is not None:
+            try:
+                kf_set_transition(self.plan, F)
+            except Exception:
+                self.close()
+                raise
 
     def filter(self, Y, want_diag: bool = True) -> Result:
         T = Y.shape[0]

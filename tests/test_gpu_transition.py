@@ -1,0 +1,117 @@
+"""Sparse transition F (eqn3; the six-neighbour model of eqn2) through the C ABI.
+
+Filter, smoother and mean-only smoother with F against the oracle run with the same
+dense F: 1e-10 normwise on the float64 path, 1e-4 mixed; checkpoint-recompute equal
+to the full store bit for bit; F = I given explicitly equal to the random walk.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1107_4192_amd import kfmeg, synth
+from _helpers import dev, eps_P, eps_d, eps_x, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_run(p, full=False, **opt):
+    ks = kfmeg.KalmanSmoother(dev(p.X), dev(p.Q), dev(p.R), dev(p.x0), dev(p.P0), T_max=p.T, F=p.F, **opt)
+    try:
+        res = ks.run(dev(p.Y), want_full=full)
+        filt = [to_np(ks.filtered_cov(t + 1)) for t in range(p.T)] if full else None
+    finally:
+        ks.close()
+    return res, filt
+
+
+def oracle_run(p):
+    F = p.F_dense()
+    xf, Pf, dPf = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=F)
+    xs, Ps, dPs = oracle.rts_smooth(xf, Pf, p.Q, F=F)
+    return xf, Pf, dPf, xs, Ps, dPs
+
+
+@pytest.mark.parametrize("seed,N,m,T,density", [(1, 5, 3, 4, 1.0), (2, 20, 6, 8, 0.3), (3, 130, 7, 5, 0.05),
+                                                (4, 257, 130, 4, 0.02), (5, 1, 1, 5, 1.0)])
+def test_random_transition_vs_oracle(seed, N, m, T, density):
+    p = synth.small_random_F(seed, N, m, T, density)
+    res, filt = gpu_run(p, full=True)
+    xf, Pf, dPf, xs, Ps, dPs = oracle_run(p)
+    errs = {"x_filt": eps_x(res.x_filt, xf), "P_filt": eps_P(np.stack(filt), Pf),
+            "x_smooth": eps_x(res.x_smooth, xs), "P_smooth": eps_P(res.P_smooth, Ps),
+            "d_smooth": eps_d(res.Pdiag_smooth, dPs)}
+    assert max(errs.values()) <= 1e-10, errs
+    if N * T <= 200:
+        bf = oracle.joint_posterior(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=p.F_dense())
+        assert eps_x(res.x_smooth, bf[2]) <= 1e-10
+
+
+def test_neighbourhood_tiny_precisions_checkpointing_batch_and_means():
+    p = synth.neighbourhood(N=500, m=60, T=12)
+    xf, Pf, dPf, xs, Ps, dPs = oracle_run(p)
+    full, _ = gpu_run(p)
+    assert eps_x(full.x_filt, xf) <= 1e-10 and eps_x(full.x_smooth, xs) <= 1e-10
+    assert eps_d(full.Pdiag_smooth, dPs) <= 1e-10
+    ck, _ = gpu_run(p, checkpoint_stride=4)
+    assert torch.equal(ck.x_smooth, full.x_smooth) and torch.equal(ck.Pdiag_smooth, full.Pdiag_smooth)
+    # Mixed precision: the eqn13 products run in float32. This F (half of it a neighbour
+    # average) leaves P_{t+1|t} about 1e3 times worse conditioned than the random walk does
+    # (cond ~1.7e5 against ~1.6e2 at t = 5), and the smoothed variances, some 20 times smaller,
+    # come out at a normwise error of about 3e-4 -- the means stay at 2e-7. The bound for
+    # diag P_{t|T} is therefore 1e-3 here, against 1e-4 for the random walk.
+    for store32 in (False, True):
+        mixed, _ = gpu_run(p, precision=kfmeg.KF_MIXED, store_fp32=store32)
+        e = (eps_x(mixed.x_smooth, xs), eps_d(mixed.Pdiag_smooth, dPs), eps_d(mixed.Pdiag_filt, dPf))
+        print("neighbourhood mixed errors (x_smooth, diag P_smooth, diag P_filt), float32 store:", store32, e)
+        assert e[0] <= 1e-4 and e[1] <= 1e-3 and e[2] <= 1e-4
+    # batched data sets and the mean-only smoother under the same F
+    rng = np.random.default_rng(9)
+    Ys = np.stack([p.Y, p.Y + np.std(p.Y) * rng.normal(size=p.Y.shape)])
+    ks = kfmeg.KalmanSmoother(dev(p.X), dev(p.Q), dev(p.R), dev(p.x0), dev(p.P0), T_max=p.T, F=p.F,
+                              keep_gain_factors=True)
+    try:
+        res = ks.run_batch(dev(Ys))
+        xs_means = torch.empty_like(res.x_filt)
+        kfmeg.kf_smooth_means(ks.plan, xs_means)
+    finally:
+        ks.close()
+    for b in range(2):
+        xf_b, Pf_b, _ = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, Ys[b], F=p.F_dense())
+        xs_b = oracle.rts_smooth(xf_b, Pf_b, p.Q, F=p.F_dense())[0]
+        assert eps_x(res.x_smooth[b], xs_b) <= 1e-10, b
+        assert eps_x(xs_means[b], xs_b) <= 1e-10, b
+
+
+def test_identity_transition_is_random_walk():
+    p = synth.small_random(31, 140, 12, 6)
+    walk, _ = gpu_run(p)
+    p.F = synth.dense_to_csr(np.eye(p.N))
+    eye, _ = gpu_run(p)
+    assert eps_x(eye.x_smooth, to_np(walk.x_smooth)) <= 1e-13
+    assert eps_d(eye.Pdiag_smooth, to_np(walk.Pdiag_smooth)) <= 1e-13
+
+
+def test_neighbourhood_paper_scale_short_horizon():
+    p = synth.neighbourhood(T=3)
+    res, _ = gpu_run(p)
+    xf, Pf, dPf, xs, Ps, dPs = oracle_run(p)
+    errs = {"x_filt": eps_x(res.x_filt, xf), "x_smooth": eps_x(res.x_smooth, xs),
+            "d_smooth": eps_d(res.Pdiag_smooth, dPs)}
+    print("paper-scale neighbourhood errors", errs)
+    assert max(errs.values()) <= 1e-10, errs
+
+
+def test_malformed_transition_rejected():
+    p = synth.small_random(32, 10, 3, 3)
+    rp, ci, v = synth.dense_to_csr(np.eye(10))
+    bad = ci.copy()
+    bad[3] = 10                                           # column out of range
+    ks = kfmeg.KalmanSmoother(dev(p.X), dev(p.Q), dev(p.R), dev(p.x0), dev(p.P0), T_max=3)
+    try:
+        with pytest.raises(kfmeg.KFError) as ei:
+            kfmeg.kf_set_transition(ks.plan, (rp, bad, v))
+        assert ei.value.status == kfmeg.KF_EINVAL
+        kfmeg.kf_set_transition(ks.plan, (rp, ci, v))    # a valid one is accepted afterwards
+    finally:
+        ks.close()
