@@ -209,8 +209,11 @@ kf_status kf_set_profiling(kf_plan* plan, int on);
 kf_status kf_get_profile(const kf_plan* plan, double* kernel_ms, double* kernel_flops, int64_t* launches);
 
 /*
- * Device bytes a plan of this shape would allocate: workspaces plus the full
- * covariance store for T steps under `opt` (used for admission decisions).
+ * Device bytes a plan of this shape would allocate with one batch of smoother
+ * gains in flight: workspaces plus the full covariance store for T steps under
+ * `opt` (serving plans are sized this way; a plan made by kf_create also forms
+ * a second gain batch on another stream when the HBM budget leaves room for
+ * its (3 gb + 1) more N x N workspaces, gb <= 8 the gain-batch width).
  */
 size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt);
 

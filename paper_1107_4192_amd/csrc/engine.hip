@@ -63,10 +63,11 @@ struct kf_plan {
     // given the stored P_{t|t}) on a second stream, one batch ahead of the back-recursion;
     // the gains, and the upcast P_{t|t} they came from, are double buffered (set 0 / 1).
     int gbatch = 1;
-    double *W[kMaxBatch] = {}, *Li[kMaxBatch] = {};
-    double* Ab[2][kMaxBatch] = {};
-    double* Pt64[2][kMaxBatch] = {};
-    float* A32[2][kMaxBatch] = {};
+    int nprod = 1;                          // gain batches in flight at once, one side stream each
+    double *W[2][kMaxBatch] = {}, *Li[2][kMaxBatch] = {};   // factorisation scratch per side stream
+    double* Ab[3][kMaxBatch] = {};          // gain sets: nprod + 1 in rotation
+    double* Pt64[3][kMaxBatch] = {};
+    float* A32[3][kMaxBatch] = {};
     double* Ps[2] = {nullptr, nullptr};
     double *Dm = nullptr, *Mm = nullptr;    // D = P_{t+1|T} - P_{t+1|t} and M = A_t D (float64 path)
     float *D32 = nullptr, *M32 = nullptr;   // the same in float32 (mixed path)
@@ -74,8 +75,8 @@ struct kf_plan {
     // P_t + M A_t^T, lower tiles), chosen once per plan
     TailSplit ts_m, ts_low;
     void* tail_ws = nullptr;
-    hipStream_t s2 = nullptr;
-    hipEvent_t ev_start = nullptr, ev_gain[2] = {nullptr, nullptr}, ev_chain[2] = {nullptr, nullptr};
+    hipStream_t s2[2] = {nullptr, nullptr};
+    hipEvent_t ev_start = nullptr, ev_gain[3] = {}, ev_chain[3] = {};
     // status
     int* dstatus = nullptr;
     int* hstatus = nullptr;
@@ -216,17 +217,19 @@ size_t factor_bytes(int64_t N, int64_t m, int64_t T) {
     return 8 * (size_t)T * ((size_t)m * ldN + (size_t)m * ldm + (size_t)ldm);
 }
 
-size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int gb) {
+// np: gain batches in flight (np scratch sets W, Li and np + 1 gain sets).
+size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int gb, int np = 1) {
     const int64_t ldN = round_up(N, 16), ldm = round_up(m, 16);
     const size_t NN = (size_t)N * ldN;
     size_t b = 0;
     b += 8 * (2 * NN + 2 * (size_t)m * ldN + (size_t)m * ldm + 2 * (size_t)N);   // Q, P0, X, XQ, R, x0
     b += 8 * (2 * (size_t)m * ldN + 2 * (size_t)m * ldm + 3 * (size_t)N + 64);
     b += 8 * (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);                 // split-K partials
-    b += 8 * (4 * (size_t)gb + 2) * NN;                                          // W, Li, 2 x A per batch; Ps x2
+    const size_t sets = (size_t)np + 1;
+    b += 8 * ((2 * (size_t)np + sets) * (size_t)gb + 2) * NN;                // W, Li per stream, A per set; Ps x2
     if (!mix) b += 8 * 2 * NN;                                                   // D, M
-    if (s32) b += 8 * 2 * (size_t)gb * NN;                                       // upcast P_{t|t}
-    if (mix) b += 4 * (2 * (size_t)gb * NN + 2 * NN + (size_t)m * ldN);     // A32, D32, M32, Cm32
+    if (s32) b += 8 * sets * (size_t)gb * NN;                                    // upcast P_{t|t}
+    if (mix) b += 4 * (sets * (size_t)gb * NN + 2 * NN + (size_t)m * ldN);  // A32, D32, M32, Cm32
     if (s32 || stride > 1) b += 8 * 2 * NN;
     if (mix) b += 4 * NN;
     if (stride > 1) b += (size_t)stride * NN * (s32 ? 4 : 8);
@@ -543,11 +546,15 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     const bool mix = mixed(p);
     p->keep = p->opt.keep_gain_factors != 0;
     const size_t fac = p->keep ? factor_bytes(N, m, T_max) : 0;
+    int np = arena ? 1 : 2;                 // serving plans keep one gain batch in flight
     auto need = [&](int st, int gb) {
-        return workspace_bytes(N, m, mix, p->store32, st, gb) + store_bytes(N, p->ldN, T_max, p->store32, st) + fac;
+        return workspace_bytes(N, m, mix, p->store32, st, gb, np) + store_bytes(N, p->ldN, T_max, p->store32, st) +
+               fac;
     };
-    // Prefer storing every P_{t|t}; give up gain batching before checkpointing.
+    // Prefer storing every P_{t|t}; give up the second gain batch in flight, then gain
+    // batching, before checkpointing.
     int gb = kMaxBatch;
+    if (np == 2 && need(stride, gb) > budget) np = 1;
     while (gb > 1 && need(stride, gb) > budget) gb /= 2;
     if (p->opt.checkpoint_stride <= 0) {
         while (stride < T_max && need(stride, gb) > budget)
@@ -559,6 +566,7 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
         return KF_ENOMEM;
     }
     p->gbatch = gb;
+    p->nprod = np;
     p->stride = stride;
     p->nslots = slots_needed(T_max, stride);
 
@@ -579,8 +587,8 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     ALLOC(p->partial, p->partial_elems);
     ALLOC(p->dstatus, 4);
     for (int b = 0; b < p->gbatch; ++b) {
-        ALLOC(p->W[b], NN); ALLOC(p->Li[b], NN);
-        for (int set = 0; set < 2; ++set) {
+        for (int q = 0; q < p->nprod; ++q) { ALLOC(p->W[q][b], NN); ALLOC(p->Li[q][b], NN); }
+        for (int set = 0; set <= p->nprod; ++set) {
             ALLOC(p->Ab[set][b], NN);
             if (p->store32) ALLOC(p->Pt64[set][b], NN);
             if (mix) ALLOC(p->A32[set][b], NN);
@@ -624,14 +632,16 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
         p->err = "pinned host allocation failed";
         return fail(KF_ENOMEM);
     }
-    if (hipStreamCreateWithFlags(&p->s2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_gain[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_gain[1], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_chain[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_chain[1], hipEventDisableTiming) != hipSuccess) {
-        p->err = "kf_create: creating the side stream or its events failed";
-        return fail(KF_EHIP);
+    {
+        bool ok = hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming) == hipSuccess;
+        for (int q = 0; ok && q < p->nprod; ++q) ok = hipStreamCreateWithFlags(&p->s2[q], hipStreamNonBlocking) == hipSuccess;
+        for (int k = 0; ok && k < 3; ++k)
+            ok = hipEventCreateWithFlags(&p->ev_gain[k], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&p->ev_chain[k], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            p->err = "kf_create: creating the side streams or their events failed";
+            return fail(KF_EHIP);
+        }
     }
     hipStream_t s = p->stream;
     auto cp = [&](void* dst, bool d32, int64_t ldd, const double* src, int64_t rows, int64_t cols) {
@@ -798,8 +808,10 @@ kf_status recompute_segment(kf_plan* p, int64_t t0, int64_t t1, int64_t T) {
 // t = ts[b], formed as G = Li P_t, A_t = G^T Li with L Li = chol(P_t + Q), into gain set
 // `set`. The steps are independent given the stored P_{t|t}, so every launch covers the
 // whole batch.
-kf_status gain_batch(kf_plan* p, int set, int count, const int64_t* ts, const void* const* Pt, const bool* is32,
-                     hipStream_t s) {
+kf_status gain_batch(kf_plan* p, int set, int q, int count, const int64_t* ts, const void* const* Pt,
+                     const bool* is32, hipStream_t s) {
+    double* const* Wq = p->W[q];
+    double* const* Liq = p->Li[q];
     const int N = (int)p->N;
     const int64_t ld = p->ldN;
     const double* P64[kMaxBatch];
@@ -813,31 +825,31 @@ kf_status gain_batch(kf_plan* p, int set, int count, const int64_t* ts, const vo
         if (p->hasF) {
             // G_t = P_t F^T (kept in A_t's buffer until A_t overwrites it); W = F G_t + Q (eqn7)
             HIPCK(dense_sparse_t(p->F, P64[b], ld, p->Ab[set][b], ld, s));
-            HIPCK(spmm_rows(p->F, p->Ab[set][b], ld, 1.0, p->Q, ld, 1.0, nullptr, 0, 0.0, p->W[b], false, ld, s));
+            HIPCK(spmm_rows(p->F, p->Ab[set][b], ld, 1.0, p->Q, ld, 1.0, nullptr, 0, 0.0, Wq[b], false, ld, s));
         } else {
             // W = P_t + Q  (= P_{t+1|t}, eqn7)
-            HIPCK(axpby3(N, N, p->W[b], false, ld, P64[b], false, ld, p->Q, false, ld, 1.0, nullptr, false, 0, 0.0,
+            HIPCK(axpby3(N, N, Wq[b], false, ld, P64[b], false, ld, p->Q, false, ld, 1.0, nullptr, false, 0, 0.0,
                          s));
         }
         steps[b] = (int)ts[b] + 1;
     }
-    HIPCK(chol_inv_batch(N, p->W, ld, p->Li, ld, count, p->dstatus, W_PPRED, steps, s));
+    HIPCK(chol_inv_batch(N, Wq, ld, Liq, ld, count, p->dstatus, W_PPRED, steps, s));
     // A_t = P_t Li^T Li. H = P_t Li^T goes into W (L is not needed any more); Li is then
     // transposed in place so that both products read their second operand row-contiguous.
     GemmProblem g[kMaxBatch], h[kMaxBatch];
     for (int b = 0; b < count; ++b) {
         g[b].M = N; g[b].N = N; g[b].K = N;    // H = P_t F^T Li^T   (B(l,k) = Li[k][l], zero for l > k)
         g[b].A = p->hasF ? p->Ab[set][b] : P64[b]; g[b].lda = ld;
-        g[b].B = p->Li[b]; g[b].ldb = ld; g[b].flags = G_TB | G_BUPPER;
-        g[b].C = p->W[b]; g[b].ldc = ld;
+        g[b].B = Liq[b]; g[b].ldb = ld; g[b].flags = G_TB | G_BUPPER;
+        g[b].C = Wq[b]; g[b].ldc = ld;
         h[b].M = N; h[b].N = N; h[b].K = N;    // A_t = H Li     (B(k,j) = Li[k][j] = LiT[j][k])
-        h[b].A = p->W[b]; h[b].lda = ld;
-        h[b].B = p->Li[b]; h[b].ldb = ld; h[b].flags = G_TB | G_BLOWER;
+        h[b].A = Wq[b]; h[b].lda = ld;
+        h[b].B = Liq[b]; h[b].ldb = ld; h[b].flags = G_TB | G_BLOWER;
         h[b].C = p->Ab[set][b]; h[b].ldc = ld;
         if (mixed(p)) { h[b].C32 = p->A32[set][b]; h[b].ldc32 = ld; }
     }
     TRY(big_group(p, Dt::F64, g, count, (double)count * N * N * N, s));
-    for (int b = 0; b < count; ++b) HIPCK(transpose_inplace(p->Li[b], ld, N, s));
+    for (int b = 0; b < count; ++b) HIPCK(transpose_inplace(Liq[b], ld, N, s));
     TRY(big_group(p, Dt::F64, h, count, (double)count * N * N * N, s));
     return KF_OK;
 }
@@ -951,22 +963,24 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
             batches.push_back(bt);
             t -= bt.count;
         }
+        // Batch k is formed on side stream k % nprod into gain set k % (nprod + 1); the
+        // back-recursion consumes the sets in order, and a set is formed again only after the
+        // chain that read it has been enqueued and has recorded its event.
         HIPCK(hipEventRecord(p->ev_start, s));
-        HIPCK(hipStreamWaitEvent(p->s2, p->ev_start, 0));
+        for (int q = 0; q < p->nprod; ++q) HIPCK(hipStreamWaitEvent(p->s2[q], p->ev_start, 0));
         const size_t nb = batches.size();
-        if (nb > 0) {
-            TRY(gain_batch(p, 0, batches[0].count, batches[0].ts, batches[0].Pt, batches[0].is32, p->s2));
-            HIPCK(hipEventRecord(p->ev_gain[0], p->s2));
-        }
+        const int np = p->nprod, ns = p->nprod + 1;
+        auto produce = [&](size_t k) -> kf_status {
+            const int q = (int)(k % np), set = (int)(k % ns);
+            if (k >= (size_t)ns) HIPCK(hipStreamWaitEvent(p->s2[q], p->ev_chain[set], 0));   // chain k - ns done
+            TRY(gain_batch(p, set, q, batches[k].count, batches[k].ts, batches[k].Pt, batches[k].is32, p->s2[q]));
+            HIPCK(hipEventRecord(p->ev_gain[set], p->s2[q]));
+            return KF_OK;
+        };
+        for (size_t k = 0; k < nb && k < (size_t)np; ++k) TRY(produce(k));
         for (size_t k = 0; k < nb; ++k) {
-            if (k + 1 < nb) {
-                const int set = (int)((k + 1) & 1);
-                if (k >= 1) HIPCK(hipStreamWaitEvent(p->s2, p->ev_chain[set], 0));   // chain k-1 released it
-                TRY(gain_batch(p, set, batches[k + 1].count, batches[k + 1].ts, batches[k + 1].Pt,
-                               batches[k + 1].is32, p->s2));
-                HIPCK(hipEventRecord(p->ev_gain[set], p->s2));
-            }
-            const int set = (int)(k & 1);
+            if (k + np < nb) TRY(produce(k + np));
+            const int set = (int)(k % ns);
             HIPCK(hipStreamWaitEvent(s, p->ev_gain[set], 0));
             TRY(run_chain(set, batches[k].count, batches[k].ts, batches[k].Pt));
             HIPCK(hipEventRecord(p->ev_chain[set], s));
@@ -998,7 +1012,7 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
                 is32[count] = kept(p, t - count, T) ? !slot64(p) : s32;   // checkpoints float64, segment as stored
                 ++count;
             }
-            TRY(gain_batch(p, 0, count, ts, Pt, is32, s));
+            TRY(gain_batch(p, 0, 0, count, ts, Pt, is32, s));
             TRY(run_chain(0, count, ts, Pt));
             t -= count;
         }
@@ -1279,10 +1293,13 @@ void kf_destroy(kf_plan* p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     else (void)hipDeviceSynchronize();
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
-    if (p->s2) (void)hipStreamSynchronize(p->s2);
-    for (hipEvent_t e : {p->ev_start, p->ev_gain[0], p->ev_gain[1], p->ev_chain[0], p->ev_chain[1]})
+    for (hipStream_t q : p->s2)
+        if (q) (void)hipStreamSynchronize(q);
+    for (hipEvent_t e : {p->ev_start, p->ev_gain[0], p->ev_gain[1], p->ev_gain[2], p->ev_chain[0], p->ev_chain[1],
+                         p->ev_chain[2]})
         if (e) (void)hipEventDestroy(e);
-    if (p->s2) (void)hipStreamDestroy(p->s2);
+    for (hipStream_t q : p->s2)
+        if (q) (void)hipStreamDestroy(q);
     for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb, p->Ub})
         if (b) (void)hipFree(b);
     for (double* b : p->bfac_w) (void)hipFree(b);
