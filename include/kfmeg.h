@@ -213,7 +213,7 @@ kf_status kf_get_profile(const kf_plan* plan, double* kernel_ms, double* kernel_
  * gains in flight: workspaces plus the full covariance store for T steps under
  * `opt` (serving plans are sized this way; a plan made by kf_create also forms
  * a second gain batch on another stream when the HBM budget leaves room for
- * its (3 gb + 1) more N x N workspaces, gb <= 8 the gain-batch width).
+ * its 3 gb or more extra N x N workspaces, gb <= 8 the gain-batch width).
  */
 size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt);
 

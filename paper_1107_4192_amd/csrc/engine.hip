@@ -64,10 +64,10 @@ struct kf_plan {
     // the gains, and the upcast P_{t|t} they came from, are double buffered (set 0 / 1).
     int gbatch = 1;
     int nprod = 1;                          // gain batches in flight at once, one side stream each
-    double *W[2][kMaxBatch] = {}, *Li[2][kMaxBatch] = {};   // factorisation scratch per side stream
-    double* Ab[3][kMaxBatch] = {};          // gain sets: nprod + 1 in rotation
-    double* Pt64[3][kMaxBatch] = {};
-    float* A32[3][kMaxBatch] = {};
+    double *W[kMaxProd][kMaxBatch] = {}, *Li[kMaxProd][kMaxBatch] = {};   // factorisation scratch per stream
+    double* Ab[kMaxProd + 1][kMaxBatch] = {};   // gain sets: nprod + 1 in rotation
+    double* Pt64[kMaxProd + 1][kMaxBatch] = {};
+    float* A32[kMaxProd + 1][kMaxBatch] = {};
     double* Ps[2] = {nullptr, nullptr};
     double *Dm = nullptr, *Mm = nullptr;    // D = P_{t+1|T} - P_{t+1|t} and M = A_t D (float64 path)
     float *D32 = nullptr, *M32 = nullptr;   // the same in float32 (mixed path)
@@ -75,8 +75,8 @@ struct kf_plan {
     // P_t + M A_t^T, lower tiles), chosen once per plan
     TailSplit ts_m, ts_low;
     void* tail_ws = nullptr;
-    hipStream_t s2[2] = {nullptr, nullptr};
-    hipEvent_t ev_start = nullptr, ev_gain[3] = {}, ev_chain[3] = {};
+    hipStream_t s2[kMaxProd] = {};
+    hipEvent_t ev_start = nullptr, ev_gain[kMaxProd + 1] = {}, ev_chain[kMaxProd + 1] = {};
     // status
     int* dstatus = nullptr;
     int* hstatus = nullptr;
@@ -546,7 +546,7 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     const bool mix = mixed(p);
     p->keep = p->opt.keep_gain_factors != 0;
     const size_t fac = p->keep ? factor_bytes(N, m, T_max) : 0;
-    int np = arena ? 1 : 2;                 // serving plans keep one gain batch in flight
+    int np = arena ? 1 : kMaxProd;          // serving plans keep one gain batch in flight
     auto need = [&](int st, int gb) {
         return workspace_bytes(N, m, mix, p->store32, st, gb, np) + store_bytes(N, p->ldN, T_max, p->store32, st) +
                fac;
@@ -554,7 +554,7 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     // Prefer storing every P_{t|t}; give up the second gain batch in flight, then gain
     // batching, before checkpointing.
     int gb = kMaxBatch;
-    if (np == 2 && need(stride, gb) > budget) np = 1;
+    while (np > 1 && need(stride, gb) > budget) --np;
     while (gb > 1 && need(stride, gb) > budget) gb /= 2;
     if (p->opt.checkpoint_stride <= 0) {
         while (stride < T_max && need(stride, gb) > budget)
@@ -635,7 +635,7 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     {
         bool ok = hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming) == hipSuccess;
         for (int q = 0; ok && q < p->nprod; ++q) ok = hipStreamCreateWithFlags(&p->s2[q], hipStreamNonBlocking) == hipSuccess;
-        for (int k = 0; ok && k < 3; ++k)
+        for (int k = 0; ok && k <= p->nprod; ++k)
             ok = hipEventCreateWithFlags(&p->ev_gain[k], hipEventDisableTiming) == hipSuccess &&
                  hipEventCreateWithFlags(&p->ev_chain[k], hipEventDisableTiming) == hipSuccess;
         if (!ok) {
@@ -1295,9 +1295,11 @@ void kf_destroy(kf_plan* p) {
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     for (hipStream_t q : p->s2)
         if (q) (void)hipStreamSynchronize(q);
-    for (hipEvent_t e : {p->ev_start, p->ev_gain[0], p->ev_gain[1], p->ev_gain[2], p->ev_chain[0], p->ev_chain[1],
-                         p->ev_chain[2]})
-        if (e) (void)hipEventDestroy(e);
+    if (p->ev_start) (void)hipEventDestroy(p->ev_start);
+    for (int k = 0; k <= kMaxProd; ++k) {
+        if (p->ev_gain[k]) (void)hipEventDestroy(p->ev_gain[k]);
+        if (p->ev_chain[k]) (void)hipEventDestroy(p->ev_chain[k]);
+    }
     for (hipStream_t q : p->s2)
         if (q) (void)hipStreamDestroy(q);
     for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb, p->Ub})

@@ -44,6 +44,7 @@ struct GemmProblem {
 
 constexpr int kMaxGroup = 16;
 constexpr int kMaxBatch = 8;   // matrices per batched factorisation (two problems each per group)
+constexpr int kMaxProd = 2;    // smoother gain batches in flight at once (side streams)
 
 enum class Dt { F64, F32 };
 
