@@ -205,7 +205,7 @@ def run_batched(p, B, steps):
 
 
 def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(102, 204, 306),
-                T_range=(20, 60), max_active=4):
+                T_range=(20, 60), max_active=4, budget_gib=0.0):
     """Serving form: Poisson arrivals of filter+smoother jobs of mixed shapes, mixed precision
     with float32 stores, continuously batched; against the same jobs one at a time in FP64."""
     import numpy as np
@@ -222,7 +222,8 @@ def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(
         jobs.append((j, tuple(dev(a) for a in (p.X, p.Q, p.R, p.x0, p.P0, p.Y))))
     log(f"serving: {n_jobs} jobs generated in {time.perf_counter() - t0:.1f} s")
     # continuous batching, mixed precision + float32 store
-    srv = kfmeg.Server(max_active=max_active, precision=kfmeg.KF_MIXED, store_fp32=True)
+    srv = kfmeg.Server(hbm_budget_bytes=int(budget_gib * 2 ** 30), max_active=max_active,
+                       precision=kfmeg.KF_MIXED, store_fp32=True)
     ids = []
     start = time.perf_counter()
     for j, arrs in jobs:
@@ -248,7 +249,8 @@ def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(
     steps = sum(j["T"] for j, _ in jobs)
     log(f"serving: sequential FP64 {seq:.1f} s")
     return {"workload": f"{n_jobs} jobs, Poisson arrivals {rate}/s, N in {list(N_choices)}, "
-                        f"m in {list(m_choices)}, T in {list(T_range)}; mixed precision, float32 store",
+                        f"m in {list(m_choices)}, T in {list(T_range)}; mixed precision, float32 store"
+                        + (f", HBM budget {budget_gib:g} GiB" if budget_gib else ""),
             "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "jobs_per_s": st["jobs_per_s"],
             "steps_per_s": st["steps_per_s"], "max_concurrent": st["max_concurrent"],
             "checkpointed": st["checkpointed"], "peak_gib": st["peak_bytes"] / 2 ** 30,
@@ -311,8 +313,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="run a 256 MiB copy first (HBM counter scale)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the mean-only and batched legs")
-    ap.add_argument("--workload", choices=("paper", "free"), default="paper",
-                    help="free: run the free-orientation N=15372 workload only (full store and checkpointed)")
+    ap.add_argument("--workload", choices=("paper", "free", "serving"), default="paper",
+                    help="free: the free-orientation N=15372 workload only (full store and checkpointed); "
+                         "serving: a larger serving run only (48 jobs up to N=8196 under a 96 GiB budget)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the multi-GPU sharding "
@@ -328,6 +331,11 @@ def main():
 
     if args.workload == "free":
         print(json.dumps({"free_orientation": run_free(T=min(args.T, 100))}), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps({"serving_large": run_serving(n_jobs=48, seed=7, rate=2.0, N_choices=(2000, 5124, 8196),
+                                                       T_range=(50, 150), max_active=4, budget_gib=96.0)}),
+              flush=True)
         return
     if args.calib_copy:
         calibration_copy()
