@@ -1,27 +1,29 @@
 // Plan, filter, smoother and MNE entry points (the C ABI of include/kfmeg.h).
 //
 // Filter step t (eqn6-eqn10 and the covariance update after eqn10), with
-// P_prev = P_{t-1|t-1}:
-//   B   = X (P_prev + Q)                 m x N   MFMA GEMM, split-K, P + Q fused into the B loads
+// P_prev = P_{t-1|t-1} and P_pred = P_prev + Q (F = I) or F P_prev F^T + Q:
+//   B   = X P_pred                       m x N   MFMA GEMM, split-K (F = I: X P_prev + X Q, X Q formed once)
 //   S   = B X^T + R                      m x m   MFMA GEMM, split-K (fixed-order reduction)
 //   L Li = chol(S)                        m x m   blocked Cholesky fused with L^{-1}
 //   C   = Li B                           m x N   triangular MFMA product (K range trimmed)
-//   x  += C^T (Li (y_t - X x))                   three wave-reduction kernels
-//   P_t = P_prev + Q - C^T C             N x N   lower tiles only, mirrored store (exact symmetry),
+//   x  += C^T (Li (y_t - X x_pred))               three wave-reduction kernels (B-row products
+//                                                 for several data sets)
+//   P_t = P_pred - C^T C                 N x N   lower tiles only, mirrored store (exact symmetry),
 //                                                diagonal out, written straight into store slot t
 // since K = P_pred X^T S^{-1} = C^T Li and K X P_pred = C^T C.
 //
-// Smoother step t (eqn11-eqn13, RTS reading), P_t = P_{t|t}, Pn = P_t + Q = P_{t+1|t}:
-//   L Li = chol(Pn)                      N x N   blocked Cholesky fused with L^{-1}
-//   G   = Li P_t ;  A_t = G^T Li         N x N   two triangular MFMA products: A_t = P_t Pn^{-1}
-//   x_{t|T} = x_{t|t} + A_t (x_{t+1|T} - x_{t|t})
-//   M   = A_t (P_{t+1|T} - P_t - Q)      N x N   MFMA GEMM, difference fused into the B loads
+// Smoother step t (eqn11-eqn13, RTS reading), P_t = P_{t|t}, Pn = P_{t+1|t}:
+//   L Li = chol(Pn)                      N x N   blocked Cholesky fused with L^{-1}, eight steps
+//                                                per batch, batches formed on side streams
+//   H   = (P_t F^T) Li^T ;  A_t = H Li   N x N   two triangular MFMA products: A_t = P_t F^T Pn^{-1}
+//   x_{t|T} = x_{t|t} + A_t (x_{t+1|T} - F x_{t|t})
+//   D   = P_{t+1|T} - Pn ;  M = A_t D    N x N   elementwise pass, MFMA GEMM (last wave split along K)
 //   P_{t|T} = P_t + M A_t^T              N x N   lower tiles + mirror, diagonal out
 //
-// Mixed precision runs the N x N products that involve no factor (X P, the
-// downdate C^T C, M and M A^T) on FP32 MFMA with FP32 accumulation, keeps the
-// Cholesky of S and of P_{t+1|t}, the gain A_t and every epilogue in FP64, and
-// may store P_{t|t} in FP32.
+// Mixed precision runs the downdate C^T C and the eqn13 products M and M A^T on FP32 MFMA with
+// FP32 accumulation, keeps X P_pred, the Cholesky of S and of P_{t+1|t}, the gain A_t and every
+// epilogue in FP64, and may store P_{t|t} in FP32. The mean-only smoother (kf_smooth_means)
+// replaces the smoother step by one N x N matrix-vector product per step over kept gain factors.
 #include "kf_internal.h"
 #include "arena.h"
 #include "../../include/kfmeg.h"
@@ -60,8 +62,8 @@ struct kf_plan {
     void* seg = nullptr;
     // smoother workspace
     // Smoother gains are formed for up to `gbatch` time steps at once (they are independent
-    // given the stored P_{t|t}) on a second stream, one batch ahead of the back-recursion;
-    // the gains, and the upcast P_{t|t} they came from, are double buffered (set 0 / 1).
+    // given the stored P_{t|t}) on `nprod` side streams, ahead of the back-recursion; the
+    // gains, and the upcast P_{t|t} they came from, rotate through nprod + 1 sets.
     int gbatch = 1;
     int nprod = 1;                          // gain batches in flight at once, one side stream each
     double *W[kMaxProd][kMaxBatch] = {}, *Li[kMaxProd][kMaxBatch] = {};   // factorisation scratch per stream
