@@ -180,6 +180,60 @@ def run_mean_only(p, steps, xs_ref):
             "what": "kf_filter + kf_smooth_means: smoothed means only, no P_{t|T}"}
 
 
+def run_assoc(p, t_rts, xs_ref, ds_ref):
+    """kf_smooth_assoc (time-parallel scan) against kf_smooth: on the tiny workload (N=500, m=60) at
+    two horizons, where one step's products are too small to fill the GPU, and on the workload above."""
+    import numpy as np
+    import torch
+    from paper_1107_4192_amd import kfmeg, synth
+
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+    def smoother_times(q, reps):
+        X, Q, R, x0, P0, Y = (dev(a) for a in (q.X, q.Q, q.R, q.x0, q.P0, q.Y))
+        ks = kfmeg.KalmanSmoother(X, Q, R, x0, P0, T_max=q.T)
+        xs = torch.empty((q.T, q.N), dtype=torch.float64, device="cuda")
+        ds = torch.empty_like(xs)
+        best = {"rts": 1e30, "assoc": 1e30}
+        for _ in range(reps):
+            for form in ("rts", "assoc"):
+                r = ks.filter(Y)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                (kfmeg.kf_smooth if form == "rts" else kfmeg.kf_smooth_assoc)(ks.plan, xs, ds, None)
+                torch.cuda.synchronize()
+                best[form] = min(best[form], time.perf_counter() - a)
+        ks.close()
+        return best, xs, ds
+
+    out = {"what": "kf_smooth_assoc: smoother as a blocked associative scan over time (about 2.7x the "
+                   "products of kf_smooth, depth about 3 sqrt(T) launch groups); smoother seconds only"}
+    for T in (50, 400):
+        q = synth.tiny(T=T)
+        best, _, _ = smoother_times(q, 3)
+        out[f"tiny_N500_T{T}"] = {"rts_s": best["rts"], "assoc_s": best["assoc"],
+                                  "speedup": best["rts"] / best["assoc"]}
+        log(f"assoc tiny T={T}: rts {best['rts'] * 1e3:.1f} ms, assoc {best['assoc'] * 1e3:.1f} ms")
+    X, Q, R, x0, P0, Y = (dev(a) for a in (p.X, p.Q, p.R, p.x0, p.P0, p.Y))
+    ks = kfmeg.KalmanSmoother(X, Q, R, x0, P0, T_max=p.T)
+    xs = torch.empty((p.T, p.N), dtype=torch.float64, device="cuda")
+    ds = torch.empty_like(xs)
+    ks.filter(Y)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    kfmeg.kf_smooth_assoc(ks.plan, xs, ds, None)
+    torch.cuda.synchronize()
+    t_assoc = time.perf_counter() - a
+    ks.close()
+    ref, dref = xs_ref.cpu().numpy(), ds_ref.cpu().numpy()
+    ex = float(np.linalg.norm(xs.cpu().numpy() - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
+    ed = float((np.abs(ds.cpu().numpy() - dref).max(axis=1) / np.abs(dref).max(axis=1)).max())
+    out["paper"] = {"rts_s": t_rts, "assoc_s": t_assoc, "speedup": t_rts / t_assoc,
+                    "eps_x_smooth_vs_rts_path": ex, "eps_diagP_smooth_vs_rts_path": ed}
+    log(f"assoc paper: rts {t_rts:.2f} s, assoc {t_assoc:.2f} s")
+    return out
+
+
 def run_batched(p, B, steps):
     """B data sets through one covariance pass (kf_filter_batch + kf_smooth_batch)."""
     import numpy as np
@@ -312,7 +366,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 256 MiB copy first (HBM counter scale)")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the mean-only and batched legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mean-only, batched and associative-scan legs")
     ap.add_argument("--workload", choices=("paper", "free", "serving"), default="paper",
                     help="free: the free-orientation N=15372 workload only (full store and checkpointed); "
                          "serving: a larger serving run only (48 jobs up to N=8196 under a 96 GiB budget)")
@@ -390,6 +444,7 @@ def main():
     if not args.no_extra:
         line["mean_only"] = run_mean_only(p, max(1, args.steps), r64["x_smooth"])
         line["batched"] = run_batched(p, 8, 1)
+        line["assoc"] = run_assoc(p, r64["t_smooth"], r64["x_smooth"], r64["d_smooth"])
     if not args.no_serving:
         line["serving"] = run_serving()
     if not args.no_cpu:

@@ -146,6 +146,30 @@ kf_status kf_smooth_means(kf_plan* plan, double* x_smooth);
 kf_status kf_smooth_means_batch(kf_plan* plan, int64_t B, double* x_smooth);
 
 /*
+ * kf_smooth_assoc: the same smoothed means and covariances as kf_smooth
+ * (eqn11-eqn13, RTS reading), computed as a suffix scan over time with an
+ * associative operator instead of the step-by-step back-recursion. Step t < T
+ * contributes the element (A_t, x_{t|t} - A_t F x_{t|t}, P_{t|t} - A_t F P_{t|t})
+ * with the gain A_t of eqn11, step T the element (0, x_{T|T}, P_{T|T}); the
+ * operator is (E, g, L) o (E', g', L') = (E E', E g' + g, E L' E^T + L), and the
+ * product of the elements from t to T is (0, x_{t|T}, P_{t|T}). The scan runs in
+ * blocks of about sqrt(T) steps, so its depth is about 3 sqrt(T) groups of
+ * independent products instead of T dependent steps, at about 2.7 times the
+ * products of kf_smooth: it is the faster form when one step's products are
+ * too small to fill the GPU (small N, long T), the slower one at large N.
+ *   x_smooth, Pdiag_smooth, P_smooth as for kf_smooth.
+ * Needs a float64 plan (KF_EINVAL for mixed precision or a serving plan) whose
+ * last kf_filter call ran one data set and stored every P_{t|t} in float64 (no
+ * float32 store, no checkpointing; KF_ESTATE otherwise). Allocates (T + 15)
+ * N x ldN float64 matrices for the call (KF_ENOMEM if that fails) and
+ * overwrites the stored P_{t|t}: afterwards the plan needs a new kf_filter
+ * call before any smoother call or kf_get_filtered_cov. KF_ENOTPD as for
+ * kf_smooth.
+ */
+kf_status kf_smooth_assoc(kf_plan* plan, double* x_smooth, double* Pdiag_smooth,
+                          double* P_smooth);
+
+/*
  * kf_set_transition: use x_t = F x_{t-1} + w_t (eqn3) instead of the random
  * walk, with F (N x N) sparse in CSR form: row_ptr (N+1 int32, from 0 to nnz),
  * col_idx (nnz int32, in [0, N)), val (nnz float64), all device pointers, copied

@@ -1116,6 +1116,171 @@ kf_status smooth_means_impl(kf_plan* p, int64_t B, double* xs) {
     return sync_and_check(p, "kf_smooth_means");
 }
 
+// Time-parallel smoother: eqn12 and eqn13 regrouped as a suffix scan with an associative
+// operator. Each step t < T-1 contributes the element
+//     E_t = A_t,   g_t = x_{t|t} - A_t F x_{t|t},   L_t = P_{t|t} - A_t F P_{t|t}
+// (L_t = P_{t|t} - A_t P_{t+1|t} A_t^T, since P_{t+1|t} A_t^T = F P_{t|t}), and step T-1 the
+// element (0, x_{T|T}, P_{T|T}). With
+//     (E, g, L) o (E', g', L') = (E E', E g' + g, E L' E^T + L)
+// the suffix product from t to T-1 is (0, x_{t|T}, P_{t|T}): one RTS step is the action of an
+// element on (x_{t+1|T}, P_{t+1|T}), and composing two steps is the operator above.
+//
+// Blocks of length l = ceil(sqrt(T)): (1) suffix products inside every block, one launch group
+// per position over all blocks; (2) the block totals combined from the last block back;
+// (3) every element of a block combined with the total of the blocks after it, all at once.
+// Depth about 3 sqrt(T) launch groups instead of T steps, for about 2.7 times the products of
+// the sequential smoother: it pays when one step's products are too small to fill the GPU.
+// The elements overwrite the stored P_{t|t}; E_t lives in a separate allocation of T - 1
+// matrices made for the call.
+kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
+    hipStream_t s = p->stream;
+    const int64_t T = p->T_done, N = p->N, ld = p->ldN;
+    const int n = (int)N;
+    const size_t mat = slot_elems(p);
+    const double* xf = p->xf_last;
+    constexpr int G = kMaxBatch;                 // combines per launch group
+    const int64_t nE = T - 1;
+    const size_t need = ((size_t)nE + 2 * G) * mat * 8 + 2 * (size_t)N * 8;
+    void* block = nullptr;
+    if (hipMalloc(&block, need) != hipSuccess) {
+        (void)hipGetLastError();
+        p->err = "kf_smooth_assoc: could not allocate " + std::to_string(need >> 20) + " MiB for the scan elements";
+        return KF_ENOMEM;
+    }
+    struct Free {
+        void* b;
+        ~Free() { if (b) (void)hipFree(b); }
+    } guard{block};
+    double* base = static_cast<double*>(block);
+    std::vector<double*> E(nE), Et(G), Wt(G);
+    for (int64_t t = 0; t < nE; ++t) E[t] = base + t * mat;
+    for (int k = 0; k < G; ++k) {
+        Et[k] = base + (nE + k) * mat;
+        Wt[k] = base + (nE + G + k) * mat;
+    }
+    double* zero = base + (nE + 2 * G) * mat;
+    double* u = zero + N;
+    std::vector<double*> L(T);
+    for (int64_t t = 0; t < T; ++t) L[t] = static_cast<double*>(slot_ptr(p, t));
+    std::vector<char> ezero(T, 0);               // suffix already contains step T-1: E = 0
+    ezero[T - 1] = 1;
+
+    HIPCK(hipMemsetAsync(p->dstatus, 0, 4 * sizeof(int), s));
+    HIPCK(zero2d(1, n, zero, N, s));
+    HIPCK(hipMemcpyAsync(xs + (T - 1) * N, xf + (T - 1) * N, N * 8, hipMemcpyDeviceToDevice, s));
+
+    // Elements, gbatch steps at a time: A_t straight into E_t, then g_t and L_t (over P_{t|t}).
+    for (int64_t t0 = T - 2; t0 >= 0;) {
+        const int cnt = (int)std::min<int64_t>(p->gbatch, t0 + 1);
+        int64_t ts[kMaxBatch];
+        const void* Pt[kMaxBatch];
+        bool is32[kMaxBatch];
+        double* saved[kMaxBatch];
+        for (int b = 0; b < cnt; ++b) {
+            ts[b] = t0 - b;
+            Pt[b] = L[t0 - b];
+            is32[b] = false;
+            saved[b] = p->Ab[0][b];
+            p->Ab[0][b] = E[t0 - b];
+        }
+        const kf_status st = gain_batch(p, 0, 0, cnt, ts, Pt, is32, s);
+        for (int b = 0; b < cnt; ++b) p->Ab[0][b] = saved[b];
+        if (st != KF_OK) return st;
+        for (int b = 0; b < cnt; ++b) {
+            const int64_t t = ts[b];
+            const double* Fx = xf + t * N;
+            if (p->hasF) {
+                HIPCK(spmv_rows(p->F, xf + t * N, N, 1, u, N, s));
+                Fx = u;
+            }
+            HIPCK(gemv_smooth(E[t], ld, xf + t * N, Fx, zero, xs + t * N, n, s));    // g_t = x - A F x
+            // Wt[0] = P_t F^T (P_t itself when F = I): the slot is overwritten by L_t below
+            if (p->hasF) HIPCK(dense_sparse_t(p->F, L[t], ld, Wt[0], ld, s));
+            else HIPCK(copy2d(n, n, Wt[0], false, ld, L[t], false, ld, s));
+            GemmProblem g;
+            g.M = n; g.N = n; g.K = n;
+            g.A = E[t]; g.lda = ld; g.B = Wt[0]; g.ldb = ld; g.flags = G_TB | G_LOWER | G_MIRROR;
+            g.alpha = -1.0; g.beta = 1.0; g.Cin = L[t]; g.ldcin = ld;
+            g.C = L[t]; g.ldc = ld;
+            TRY(big_gemm(p, Dt::F64, g, (double)N * N * N, s));
+        }
+        t0 -= cnt;
+    }
+
+    // s_t <- a_t o s_r for a list of independent pairs, G at a time.
+    auto combine = [&](const std::vector<std::pair<int64_t, int64_t>>& pairs) -> kf_status {
+        for (size_t c0 = 0; c0 < pairs.size(); c0 += G) {
+            const int cnt = (int)std::min<size_t>(G, pairs.size() - c0);
+            GemmProblem g1[2 * G], g2[G];
+            int n1 = 0;
+            double f1 = 0.0;
+            for (int k = 0; k < cnt; ++k) {
+                const int64_t t = pairs[c0 + k].first, r = pairs[c0 + k].second;
+                if (!ezero[r]) {                 // E_t E_r
+                    GemmProblem e;
+                    e.M = n; e.N = n; e.K = n;
+                    e.A = E[t]; e.lda = ld; e.B = E[r]; e.ldb = ld;
+                    e.C = Et[k]; e.ldc = ld;
+                    g1[n1++] = e;
+                    f1 += 2.0 * N * N * N;
+                }
+                GemmProblem w;                   // W = E_t L_r   (L_r symmetric: read row-contiguous)
+                w.M = n; w.N = n; w.K = n;
+                w.A = E[t]; w.lda = ld; w.B = L[r]; w.ldb = ld; w.flags = G_TB;
+                w.C = Wt[k]; w.ldc = ld;
+                g1[n1++] = w;
+                f1 += 2.0 * N * N * N;
+                HIPCK(gemv_add(E[t], false, ld, xs + r * N, xs + t * N, xs + t * N, n, s));   // g_t += E_t g_r
+                GemmProblem l;                   // L_t = W E_t^T + L_t
+                l.M = n; l.N = n; l.K = n;
+                l.A = Wt[k]; l.lda = ld; l.B = E[t]; l.ldb = ld; l.flags = G_TB | G_LOWER | G_MIRROR;
+                l.beta = 1.0; l.Cin = L[t]; l.ldcin = ld;
+                l.C = L[t]; l.ldc = ld;
+                g2[k] = l;
+            }
+            for (int q = 0; q < n1; q += kMaxGroup)
+                TRY(big_group(p, Dt::F64, g1 + q, std::min(kMaxGroup, n1 - q), f1 * std::min(kMaxGroup, n1 - q) / n1,
+                              s));
+            TRY(big_group(p, Dt::F64, g2, cnt, (double)cnt * N * N * N, s));
+            for (int k = 0; k < cnt; ++k) {
+                const int64_t t = pairs[c0 + k].first, r = pairs[c0 + k].second;
+                if (ezero[r]) ezero[t] = 1;
+                else std::swap(E[t], Et[k]);     // the product becomes E_t; the old buffer is free
+            }
+        }
+        return KF_OK;
+    };
+    const int64_t len = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)T)));
+    const int64_t nb = (T + len - 1) / len;
+    auto first = [&](int64_t b) { return b * len; };
+    auto last = [&](int64_t b) { return std::min(T, (b + 1) * len) - 1; };
+    std::vector<std::pair<int64_t, int64_t>> pairs;
+    for (int64_t i = len - 2; i >= 0; --i) {             // (1) inside every block
+        pairs.clear();
+        for (int64_t b = 0; b < nb; ++b)
+            if (first(b) + i + 1 <= last(b)) pairs.emplace_back(first(b) + i, first(b) + i + 1);
+        TRY(combine(pairs));
+    }
+    for (int64_t b = nb - 2; b >= 0; --b) {              // (2) block totals, last block first
+        pairs.assign(1, {first(b), first(b + 1)});
+        TRY(combine(pairs));
+    }
+    pairs.clear();                                       // (3) the rest of every block
+    for (int64_t b = 0; b + 1 < nb; ++b)
+        for (int64_t t = first(b) + 1; t <= last(b); ++t) pairs.emplace_back(t, first(b + 1));
+    TRY(combine(pairs));
+
+    for (int64_t t = 0; t < T; ++t) {
+        if (Pdiag) HIPCK(diag_copy(L[t], ld, n, Pdiag + t * N, s));
+        if (Pfull)
+            HIPCK(hipMemcpy2DAsync(Pfull + t * N * N, N * 8, L[t], ld * 8, N * 8, N, hipMemcpyDeviceToDevice, s));
+    }
+    const kf_status st = sync_and_check(p, "kf_smooth_assoc");
+    p->T_done = 0;                                       // the stored P_{t|t} are gone
+    if (st == KF_OK && p->prof) TRY(collect_profile(p));
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1141,6 +1306,36 @@ kf_status kf_smooth_batch(kf_plan* p, int64_t B, double* x_smooth, double* Pdiag
 
 kf_status kf_smooth(kf_plan* p, double* x_smooth, double* Pdiag_smooth, double* P_smooth) {
     return kf_smooth_batch(p, 1, x_smooth, Pdiag_smooth, P_smooth);
+}
+
+kf_status kf_smooth_assoc(kf_plan* p, double* x_smooth, double* Pdiag_smooth, double* P_smooth) {
+    if (!p) return KF_EINVAL;
+    p->err.clear();
+    if (p->arena) {
+        p->err = "kf_smooth_assoc: not available on plans owned by a serving context";
+        return KF_EINVAL;
+    }
+    if (mixed(p)) {
+        p->err = "kf_smooth_assoc: needs a float64 plan (precision KF_FP64)";
+        return KF_EINVAL;
+    }
+    if (!x_smooth) {
+        p->err = "kf_smooth_assoc: x_smooth is null";
+        return KF_EINVAL;
+    }
+    if (p->T_done <= 0 || !p->xf_last) {
+        p->err = "kf_smooth_assoc: no completed kf_filter on this plan (the previous kf_smooth_assoc consumed it)";
+        return KF_ESTATE;
+    }
+    if (p->B_done != 1) {
+        p->err = "kf_smooth_assoc: the last filter call ran several data sets";
+        return KF_ESTATE;
+    }
+    if (p->store32 || p->stride != 1) {
+        p->err = "kf_smooth_assoc: needs every P_{t|t} stored in float64 (no float32 store, no checkpointing)";
+        return KF_ESTATE;
+    }
+    return smooth_assoc_impl(p, x_smooth, Pdiag_smooth, P_smooth);
 }
 
 kf_status kf_smooth_means_batch(kf_plan* p, int64_t B, double* x_smooth) {

@@ -26,7 +26,7 @@ EXPORTS = ("kf_default_options", "kf_create", "kf_filter", "kf_smooth", "kf_get_
            "kfs_create", "kfs_submit", "kfs_wait", "kfs_job_info", "kfs_get_stats", "kfs_last_error",
            "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch", "kfd_gemm_tail", "kf_smooth_means",
            "kf_smooth_means_batch", "kfs_cancel",
-           "kf_set_transition")
+           "kf_set_transition", "kf_smooth_assoc")
 
 
 class KFError(RuntimeError):
@@ -73,6 +73,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_filter.restype = ctypes.c_int
     lib.kf_smooth.argtypes = [vp, dp, dp, dp]
     lib.kf_smooth.restype = ctypes.c_int
+    lib.kf_smooth_assoc.argtypes = [vp, dp, dp, dp]
+    lib.kf_smooth_assoc.restype = ctypes.c_int
     lib.kf_set_transition.argtypes = [vp, i64, dp, dp, dp]
     lib.kf_set_transition.restype = ctypes.c_int
     lib.kf_smooth_means.argtypes = [vp, dp]
@@ -230,6 +232,16 @@ def kf_set_transition(plan: int, F) -> None:
     if rp.dtype != torch.int32 or ci.dtype != torch.int32 or v.dtype != torch.float64:
         raise TypeError("F: row_ptr and col_idx must be int32, val float64")
     _check(lib, lib.kf_set_transition(plan, int(ci.numel()), rp.data_ptr(), ci.data_ptr(), v.data_ptr()), plan)
+
+
+def kf_smooth_assoc(plan: int, x_smooth, Pdiag_smooth=None, P_smooth=None) -> None:
+    """Smoother as an associative scan over time (same outputs as kf_smooth; consumes the stored P_{t|t})."""
+    lib = load_library()
+    T, N = x_smooth.shape
+    st = lib.kf_smooth_assoc(plan, _dev(x_smooth, "x_smooth", (T, N)),
+                             _dev(Pdiag_smooth, "Pdiag_smooth", (T, N)) if Pdiag_smooth is not None else None,
+                             _dev(P_smooth, "P_smooth", (T, N, N)) if P_smooth is not None else None)
+    _check(lib, st, plan)
 
 
 def kf_smooth_means(plan: int, x_smooth) -> None:
@@ -459,6 +471,16 @@ class KalmanSmoother:
 
     def run(self, Y, want_full: bool = False) -> Result:
         return self.smooth(self.filter(Y), want_full=want_full)
+
+    def smooth_assoc(self, res: Result, want_diag: bool = True, want_full: bool = False) -> Result:
+        """kf_smooth_assoc on the last filter call: same outputs as smooth(); the plan then needs a new filter call."""
+        T = res.x_filt.shape[0]
+        dev = res.x_filt.device
+        res.x_smooth = torch.empty((T, self.N), dtype=torch.float64, device=dev)
+        res.Pdiag_smooth = torch.empty((T, self.N), dtype=torch.float64, device=dev) if want_diag else None
+        res.P_smooth = torch.empty((T, self.N, self.N), dtype=torch.float64, device=dev) if want_full else None
+        kf_smooth_assoc(self.plan, res.x_smooth, res.Pdiag_smooth, res.P_smooth)
+        return res
 
     def smooth_means(self, res: Result) -> Result:
         """x_{t|T} only (needs keep_gain_factors); res.x_filt from the last filter call."""

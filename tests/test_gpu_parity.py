@@ -52,7 +52,9 @@ def check_all(res, filt, ref, tol):
 
 
 @pytest.mark.parametrize("seed,N,m,T", [(1, 1, 1, 5), (2, 5, 3, 4), (3, 20, 6, 10), (4, 130, 7, 5),
-                                        (5, 257, 130, 4), (6, 64, 64, 3)])
+                                        (5, 257, 130, 4), (6, 64, 64, 3),
+                                        (7, 40, 130, 4),     # more sensors than sources (K = N < m)
+                                        (8, 33, 5, 1)])      # one step: the smoother has nothing to do
 def test_small_random_vs_oracle_and_brute_force(seed, N, m, T):
     p = synth.small_random(seed, N, m, T)
     res, filt = gpu_run(p, full=True)

@@ -442,3 +442,82 @@ def test_transition_pin_catches_missing_ft_in_gain():
         A = np.linalg.solve(Pn, Pf[t]).T
         xs[t] = xf[t] + A @ (xs[t + 1] - F @ xf[t])
     assert rel(xs, bf[2]) > 1e-6
+
+
+# --- Associative form of the smoother (the algebra behind kf_smooth_assoc) -----------------
+
+def _assoc_elements(xf, Pf, Q, F=None):
+    T, N = xf.shape
+    Fm = np.eye(N) if F is None else F
+    els = []
+    for t in range(T - 1):
+        A = K.smoother_gain(Pf[t], Q, F)
+        els.append((A, xf[t] - A @ Fm @ xf[t], Pf[t] - A @ Fm @ Pf[t]))
+    els.append((np.zeros((N, N)), xf[T - 1], Pf[T - 1]))
+    return els
+
+
+def _op(a, b):
+    E, g, L = a
+    E2, g2, L2 = b
+    return (E @ E2, E @ g2 + g, E @ L2 @ E.T + L)
+
+
+@pytest.mark.parametrize("with_F", [False, True])
+def test_associative_scan_reproduces_rts(with_F):
+    # Any bracketing of the suffix products gives the RTS smoother: right to left (the
+    # sequential recursion), left to right, and the blocked scan kf_smooth_assoc runs.
+    p = synth.small_random_F(21, 7, 3, 11) if with_F else synth.small_random(21, 7, 3, 11)
+    F = p.F_dense() if with_F else None
+    xf, Pf, _ = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=F)
+    xs, Ps, _ = oracle.rts_smooth(xf, Pf, p.Q, F)
+    els = _assoc_elements(xf, Pf, p.Q, F)
+    T = len(els)
+    for t in range(T):
+        acc = els[t]                                  # left to right: ((a_t o a_t+1) o a_t+2) ...
+        for u in range(t + 1, T):
+            acc = _op(acc, els[u])
+        assert np.abs(acc[0]).max() == 0.0
+        assert np.allclose(acc[1], xs[t], rtol=1e-11, atol=1e-12)
+        assert np.allclose(acc[2], Ps[t], rtol=1e-10, atol=1e-12)
+    # blocked: suffixes inside blocks, block totals from the back, then the rest of each block
+    ln = math.ceil(math.sqrt(T))
+    s = list(els)
+    starts = list(range(0, T, ln))
+    ends = [min(T, b + ln) - 1 for b in starts]
+    for b0, b1 in zip(starts, ends):
+        for t in range(b1 - 1, b0 - 1, -1):
+            s[t] = _op(s[t], s[t + 1])
+    for k in range(len(starts) - 2, -1, -1):
+        s[starts[k]] = _op(s[starts[k]], s[starts[k + 1]])
+    for k in range(len(starts) - 1):
+        for t in range(starts[k] + 1, ends[k] + 1):
+            s[t] = _op(s[t], s[starts[k + 1]])
+    for t in range(T):
+        assert np.allclose(s[t][1], xs[t], rtol=1e-11, atol=1e-12)
+        assert np.allclose(s[t][2], Ps[t], rtol=1e-10, atol=1e-12)
+
+
+def test_associative_pin_catches_planted_mistakes():
+    # The same check with a transpose dropped from the operator, or F dropped from the
+    # elements, must fail.
+    p = synth.small_random_F(22, 6, 3, 8)
+    F = p.F_dense()
+    xf, Pf, _ = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, p.Y, F=F)
+    xs, Ps, _ = oracle.rts_smooth(xf, Pf, p.Q, F)
+
+    def suffix(els, op):
+        acc = els[-1]
+        out = [acc]
+        for e in reversed(els[:-1]):
+            acc = op(e, acc)
+            out.append(acc)
+        return out[::-1]
+
+    good = suffix(_assoc_elements(xf, Pf, p.Q, F), _op)
+    assert max(np.abs(g[2] - P).max() for g, P in zip(good, Ps)) < 1e-10
+    bad_op = suffix(_assoc_elements(xf, Pf, p.Q, F), lambda a, b: (a[0] @ b[0], a[0] @ b[1] + a[1],
+                                                                     a[0] @ b[2] @ a[0] + a[2]))
+    assert max(np.abs(g[2] - P).max() for g, P in zip(bad_op, Ps)) > 1e-6
+    bad_el = suffix(_assoc_elements(xf, Pf, p.Q, None), _op)     # gains and elements without F
+    assert max(np.abs(g[1] - x).max() for g, x in zip(bad_el, xs)) > 1e-6
