@@ -206,7 +206,7 @@ def run_assoc(p, t_rts, xs_ref, ds_ref):
         ks.close()
         return best, xs, ds
 
-    out = {"what": "kf_smooth_assoc: smoother as a blocked associative scan over time (about 2.7x the "
+    out = {"what": "kf_smooth_assoc: smoother as a blocked associative scan over time (about 2x the "
                    "products of kf_smooth, depth about 3 sqrt(T) launch groups); smoother seconds only"}
     for T in (50, 400):
         q = synth.tiny(T=T)

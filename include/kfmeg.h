@@ -154,14 +154,16 @@ kf_status kf_smooth_means_batch(kf_plan* plan, int64_t B, double* x_smooth);
  * operator is (E, g, L) o (E', g', L') = (E E', E g' + g, E L' E^T + L), and the
  * product of the elements from t to T is (0, x_{t|T}, P_{t|T}). The scan runs in
  * blocks of about sqrt(T) steps, so its depth is about 3 sqrt(T) groups of
- * independent products instead of T dependent steps, at about 2.7 times the
- * products of kf_smooth: it is the faster form when one step's products are
- * too small to fill the GPU (small N, long T), the slower one at large N.
+ * independent products instead of T dependent steps, at about twice the
+ * products of kf_smooth. On one GPU kf_smooth, which already overlaps its
+ * independent gain work with the back-recursion, is the faster of the two;
+ * the scan's blocks are independent units of work for several devices.
  *   x_smooth, Pdiag_smooth, P_smooth as for kf_smooth.
  * Needs a float64 plan (KF_EINVAL for mixed precision or a serving plan) whose
  * last kf_filter call ran one data set and stored every P_{t|t} in float64 (no
- * float32 store, no checkpointing; KF_ESTATE otherwise). Allocates (T + 15)
- * N x ldN float64 matrices for the call (KF_ENOMEM if that fails) and
+ * float32 store, no checkpointing; KF_ESTATE otherwise). Allocates T + 23
+ * float64 N x N matrices (rows padded to 16 elements) for the call (KF_ENOMEM
+ * if that fails) and
  * overwrites the stored P_{t|t}: afterwards the plan needs a new kf_filter
  * call before any smoother call or kf_get_filtered_cov. KF_ENOTPD as for
  * kf_smooth.

@@ -1118,9 +1118,10 @@ kf_status smooth_means_impl(kf_plan* p, int64_t B, double* xs) {
 
 // Time-parallel smoother: eqn12 and eqn13 regrouped as a suffix scan with an associative
 // operator. Each step t < T-1 contributes the element
-//     E_t = A_t,   g_t = x_{t|t} - A_t F x_{t|t},   L_t = P_{t|t} - A_t F P_{t|t}
-// (L_t = P_{t|t} - A_t P_{t+1|t} A_t^T, since P_{t+1|t} A_t^T = F P_{t|t}), and step T-1 the
-// element (0, x_{T|T}, P_{T|T}). With
+//     E_t = A_t,   g_t = x_{t|t} - A_t F x_{t|t},   L_t = P_{t|t} - H_t H_t^T
+// with H_t = P_{t|t} F^T Li_t^T the first factor of the gain (A_t = H_t Li_t), so that
+// H_t H_t^T = A_t F P_{t|t} = A_t P_{t+1|t} A_t^T; step T-1 contributes (0, x_{T|T}, P_{T|T}).
+// With
 //     (E, g, L) o (E', g', L') = (E E', E g' + g, E L' E^T + L)
 // the suffix product from t to T-1 is (0, x_{t|T}, P_{t|T}): one RTS step is the action of an
 // element on (x_{t+1|T}, P_{t+1|T}), and composing two steps is the operator above.
@@ -1128,8 +1129,8 @@ kf_status smooth_means_impl(kf_plan* p, int64_t B, double* xs) {
 // Blocks of length l = ceil(sqrt(T)): (1) suffix products inside every block, one launch group
 // per position over all blocks; (2) the block totals combined from the last block back;
 // (3) every element of a block combined with the total of the blocks after it, all at once.
-// Depth about 3 sqrt(T) launch groups instead of T steps, for about 2.7 times the products of
-// the sequential smoother: it pays when one step's products are too small to fill the GPU.
+// The depth is about 3 sqrt(T) launch groups instead of T dependent steps, for about twice
+// the products of the step-by-step smoother (E E' inside blocks, E L' E^T everywhere).
 // The elements overwrite the stored P_{t|t}; E_t lives in a separate allocation of T - 1
 // matrices made for the call.
 kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
@@ -1138,9 +1139,10 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
     const int n = (int)N;
     const size_t mat = slot_elems(p);
     const double* xf = p->xf_last;
-    constexpr int G = kMaxBatch;                 // combines per launch group
+    constexpr int GE = kMaxGroup / 2;            // combines per launch group with an E E' product
+    constexpr int G = kMaxGroup;                 // combines per launch group without one
     const int64_t nE = T - 1;
-    const size_t need = ((size_t)nE + 2 * G) * mat * 8 + 2 * (size_t)N * 8;
+    const size_t need = ((size_t)nE + GE + G) * mat * 8 + 2 * (size_t)N * 8;
     void* block = nullptr;
     if (hipMalloc(&block, need) != hipSuccess) {
         (void)hipGetLastError();
@@ -1152,13 +1154,11 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
         ~Free() { if (b) (void)hipFree(b); }
     } guard{block};
     double* base = static_cast<double*>(block);
-    std::vector<double*> E(nE), Et(G), Wt(G);
+    std::vector<double*> E(nE), Et(GE), Wt(G);
     for (int64_t t = 0; t < nE; ++t) E[t] = base + t * mat;
-    for (int k = 0; k < G; ++k) {
-        Et[k] = base + (nE + k) * mat;
-        Wt[k] = base + (nE + G + k) * mat;
-    }
-    double* zero = base + (nE + 2 * G) * mat;
+    for (int k = 0; k < GE; ++k) Et[k] = base + (nE + k) * mat;
+    for (int k = 0; k < G; ++k) Wt[k] = base + (nE + GE + k) * mat;
+    double* zero = base + (nE + GE + G) * mat;
     double* u = zero + N;
     std::vector<double*> L(T);
     for (int64_t t = 0; t < T; ++t) L[t] = static_cast<double*>(slot_ptr(p, t));
@@ -1186,6 +1186,7 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
         const kf_status st = gain_batch(p, 0, 0, cnt, ts, Pt, is32, s);
         for (int b = 0; b < cnt; ++b) p->Ab[0][b] = saved[b];
         if (st != KF_OK) return st;
+        GemmProblem g[kMaxBatch];
         for (int b = 0; b < cnt; ++b) {
             const int64_t t = ts[b];
             const double* Fx = xf + t * N;
@@ -1194,26 +1195,27 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
                 Fx = u;
             }
             HIPCK(gemv_smooth(E[t], ld, xf + t * N, Fx, zero, xs + t * N, n, s));    // g_t = x - A F x
-            // Wt[0] = P_t F^T (P_t itself when F = I): the slot is overwritten by L_t below
-            if (p->hasF) HIPCK(dense_sparse_t(p->F, L[t], ld, Wt[0], ld, s));
-            else HIPCK(copy2d(n, n, Wt[0], false, ld, L[t], false, ld, s));
-            GemmProblem g;
-            g.M = n; g.N = n; g.K = n;
-            g.A = E[t]; g.lda = ld; g.B = Wt[0]; g.ldb = ld; g.flags = G_TB | G_LOWER | G_MIRROR;
-            g.alpha = -1.0; g.beta = 1.0; g.Cin = L[t]; g.ldcin = ld;
-            g.C = L[t]; g.ldc = ld;
-            TRY(big_gemm(p, Dt::F64, g, (double)N * N * N, s));
+            // L_t = P_t - H_t H_t^T (lower tiles + mirror) over the slot; H_t is still in W
+            g[b].M = n; g[b].N = n; g[b].K = n;
+            g[b].A = p->W[0][b]; g[b].lda = ld; g[b].B = p->W[0][b]; g[b].ldb = ld;
+            g[b].flags = G_TB | G_LOWER | G_MIRROR;
+            g[b].alpha = -1.0; g[b].beta = 1.0; g[b].Cin = L[t]; g[b].ldcin = ld;
+            g[b].C = L[t]; g[b].ldc = ld;
         }
+        TRY(big_group(p, Dt::F64, g, cnt, (double)cnt * N * N * N, s));
         t0 -= cnt;
     }
 
-    // s_t <- a_t o s_r for a list of independent pairs, G at a time.
+    // s_t <- a_t o s_r for a list of independent pairs (no r is a t of the same list), GE at a
+    // time while E E' products are needed, else G at a time.
     auto combine = [&](const std::vector<std::pair<int64_t, int64_t>>& pairs) -> kf_status {
-        for (size_t c0 = 0; c0 < pairs.size(); c0 += G) {
-            const int cnt = (int)std::min<size_t>(G, pairs.size() - c0);
-            GemmProblem g1[2 * G], g2[G];
+        for (size_t c0 = 0; c0 < pairs.size();) {
+            bool withE = false;
+            for (size_t k = c0; k < pairs.size() && k < c0 + G; ++k) withE = withE || !ezero[pairs[k].second];
+            const int cnt = (int)std::min<size_t>(withE ? GE : G, pairs.size() - c0);
+            GemmProblem g1[kMaxGroup], g2[kMaxGroup];
+            GemvAddBatch gv;
             int n1 = 0;
-            double f1 = 0.0;
             for (int k = 0; k < cnt; ++k) {
                 const int64_t t = pairs[c0 + k].first, r = pairs[c0 + k].second;
                 if (!ezero[r]) {                 // E_t E_r
@@ -1222,15 +1224,13 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
                     e.A = E[t]; e.lda = ld; e.B = E[r]; e.ldb = ld;
                     e.C = Et[k]; e.ldc = ld;
                     g1[n1++] = e;
-                    f1 += 2.0 * N * N * N;
                 }
                 GemmProblem w;                   // W = E_t L_r   (L_r symmetric: read row-contiguous)
                 w.M = n; w.N = n; w.K = n;
                 w.A = E[t]; w.lda = ld; w.B = L[r]; w.ldb = ld; w.flags = G_TB;
                 w.C = Wt[k]; w.ldc = ld;
                 g1[n1++] = w;
-                f1 += 2.0 * N * N * N;
-                HIPCK(gemv_add(E[t], false, ld, xs + r * N, xs + t * N, xs + t * N, n, s));   // g_t += E_t g_r
+                gv.A[k] = E[t]; gv.x[k] = xs + r * N; gv.y[k] = xs + t * N;          // g_t += E_t g_r
                 GemmProblem l;                   // L_t = W E_t^T + L_t
                 l.M = n; l.N = n; l.K = n;
                 l.A = Wt[k]; l.lda = ld; l.B = E[t]; l.ldb = ld; l.flags = G_TB | G_LOWER | G_MIRROR;
@@ -1238,15 +1238,15 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
                 l.C = L[t]; l.ldc = ld;
                 g2[k] = l;
             }
-            for (int q = 0; q < n1; q += kMaxGroup)
-                TRY(big_group(p, Dt::F64, g1 + q, std::min(kMaxGroup, n1 - q), f1 * std::min(kMaxGroup, n1 - q) / n1,
-                              s));
+            TRY(big_group(p, Dt::F64, g1, n1, 2.0 * N * N * N * n1, s));
+            HIPCK(gemv_add_batch(gv, cnt, ld, n, s));
             TRY(big_group(p, Dt::F64, g2, cnt, (double)cnt * N * N * N, s));
             for (int k = 0; k < cnt; ++k) {
                 const int64_t t = pairs[c0 + k].first, r = pairs[c0 + k].second;
                 if (ezero[r]) ezero[t] = 1;
                 else std::swap(E[t], Et[k]);     // the product becomes E_t; the old buffer is free
             }
+            c0 += cnt;
         }
         return KF_OK;
     };

@@ -97,6 +97,13 @@ hipError_t gemv_smooth(const double* A, int64_t lda, const double* x, const doub
 // out = x + P lam  (P: N x N float or double, ld ldp)   -- mean-only smoother
 hipError_t gemv_add(const void* P, bool p32, int64_t ldp, const double* lam, const double* x, double* out, int N,
                     hipStream_t s);
+// y_q += A_q x_q for q < count (count <= kMaxGroup), all A_q N x N with leading dimension lda.
+struct GemvAddBatch {
+    const double* A[kMaxGroup];
+    const double* x[kMaxGroup];
+    double* y[kMaxGroup];
+};
+hipError_t gemv_add_batch(const GemvAddBatch& G, int count, int64_t lda, int N, hipStream_t s);
 // u = Lower(L)^T v  (L: m x m, ld ldl)
 hipError_t trmv_lower_t(const double* L, int64_t ldl, const double* v, double* u, int m, hipStream_t s);
 // D = a + ca*b + cb*c for matrices (rows x cols); each source may be float or double

@@ -111,6 +111,28 @@ __global__ void gemv_add_kernel(const TP* P, int64_t ldp, const double* lam, con
     if (lane == 0) out[row] = x[row] + s;
 }
 
+// y_q += A_q x_q for the problems q = blockIdx.y of a batch (float64), with the row sums of
+// gemv_add_kernel; y_q may be read only by its own rows, so it may not alias another x.
+__global__ void gemv_add_batch_kernel(GemvAddBatch G, int64_t lda, int N) {
+    const int q = blockIdx.y;
+    const int row = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= N) return;
+    const double* ar = G.A[q] + (int64_t)row * lda;
+    const double* x = G.x[q];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = lane;
+    for (; k + 192 < N; k += 256) {
+        s0 += ar[k] * x[k];
+        s1 += ar[k + 64] * x[k + 64];
+        s2 += ar[k + 128] * x[k + 128];
+        s3 += ar[k + 192] * x[k + 192];
+    }
+    for (; k < N; k += 64) s0 += ar[k] * x[k];
+    const double s = wave_sum((s0 + s1) + (s2 + s3));
+    if (lane == 0) G.y[q][row] += s;
+}
+
 // u_i = sum_{k >= i} L[k][i] v_k  (L lower, m x m): u = L^T v, one thread per i.
 __global__ void trmv_lower_t_kernel(const double* L, int64_t ldl, const double* v, double* u, int m) {
     const int i = blockIdx.x * TPB + threadIdx.x;
@@ -282,6 +304,12 @@ hipError_t gemv_add(const void* P, bool p32, int64_t ldp, const double* lam, con
     else
         hipLaunchKernelGGL(gemv_add_kernel<double>, dim3((N + 3) / 4), dim3(TPB), 0, s, static_cast<const double*>(P),
                            ldp, lam, x, out, N);
+    return hipGetLastError();
+}
+
+hipError_t gemv_add_batch(const GemvAddBatch& G, int count, int64_t lda, int N, hipStream_t s) {
+    if (count < 1 || count > kMaxGroup) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gemv_add_batch_kernel, dim3((N + 3) / 4, count), dim3(TPB), 0, s, G, lda, N);
     return hipGetLastError();
 }
 
