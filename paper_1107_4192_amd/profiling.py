@@ -3,6 +3,7 @@
     python -m paper_1107_4192_amd.profiling stats <run_kernel_stats.csv> [top]
     python -m paper_1107_4192_amd.profiling traffic <fetch counter csv> <write counter csv> <kernel> <out.json> \
         [bench log of the counter run]
+    python -m paper_1107_4192_amd.profiling mfma <counter csv> <kernel trace csv> [min_ms]
 
 ``traffic`` scales the per-dispatch FETCH_SIZE and WRITE_SIZE of `kernel` by what
 the same counters read for the plain 256 MiB device copy that ``bench.py
@@ -11,6 +12,12 @@ GEMM source so that a stale figure is recognised. Given the counter run's bench 
 (its JSON line carries the algorithmic flops of the same dispatches), it also records
 HBM bytes per algorithmic flop, which ``bench.py`` scales to the flops per launch of
 its own run (whose mix of launches differs from the short counter run's).
+
+``mfma`` reads a run with SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE and the MFMA op counts
+(SQ_INSTS_VALU_MFMA_MOPS_F64 / _F32, 512 flops each) per kernel: the fraction of SIMD cycles
+the matrix cores were busy (busy cycles over 1024 SIMDs, GRBM_GUI_ACTIVE summed over the 8
+XCDs), the shader clock that GRBM_GUI_ACTIVE implies over the kernel's duration, and the
+MFMA flops it executed per second (padding of partial tiles included).
 """
 from __future__ import annotations
 
@@ -77,6 +84,34 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, bench_log: str | None =
     }
 
 
+def mfma_busy(counter_csv: str, trace_csv: str, min_ms: float = 1.0) -> str:
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    for r in csv.DictReader(open(counter_csv)):
+        per[r["Dispatch_Id"]][r["Counter_Name"]] += float(r["Counter_Value"])
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    for r in csv.DictReader(open(trace_csv)):
+        c = per.get(r["Dispatch_Id"])
+        if c is None:
+            continue
+        a = agg[r["Kernel_Name"]]
+        a["n"] += 1
+        a["dur"] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+        for k, v in c.items():
+            a[k] += v
+    lines = [f"{'kernel':60s} {'launches':>8s} {'total_ms':>9s} {'clock_GHz':>9s} {'mfma_busy':>9s} "
+             f"{'exec_TFLOP/s':>12s}"]
+    for name, a in sorted(agg.items(), key=lambda kv: -kv[1]["dur"]):
+        if a["dur"] * 1e3 < min_ms:
+            continue
+        cyc = a["GRBM_GUI_ACTIVE"] / 8.0
+        busy = a["SQ_VALU_MFMA_BUSY_CYCLES"] / 1024.0 / cyc if cyc else 0.0
+        flops = 512.0 * (a["SQ_INSTS_VALU_MFMA_MOPS_F64"] + a["SQ_INSTS_VALU_MFMA_MOPS_F32"])
+        short = name.replace("kfmeg::", "").replace("(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"{short[:60]:60s} {int(a['n']):8d} {a['dur'] * 1e3:9.2f} {cyc / a['dur'] / 1e9:9.2f} "
+                     f"{busy:9.3f} {flops / a['dur'] / 1e12:12.1f}")
+    return "\n".join(lines)
+
+
 def main(argv):
     if argv[1] == "stats":
         print(kernel_stats_summary(argv[2], int(argv[3]) if len(argv) > 3 else 15))
@@ -85,6 +120,8 @@ def main(argv):
         with open(argv[5], "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps({k: v for k, v in d.items() if k != "per_dispatch_bytes"}, indent=1))
+    elif argv[1] == "mfma":
+        print(mfma_busy(argv[2], argv[3], float(argv[4]) if len(argv) > 4 else 1.0))
     else:
         raise SystemExit(__doc__)
 
