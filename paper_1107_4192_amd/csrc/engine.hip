@@ -23,7 +23,8 @@
 // Mixed precision runs the downdate C^T C and the eqn13 products M and M A^T on FP32 MFMA with
 // FP32 accumulation, keeps X P_pred, the Cholesky of S and of P_{t+1|t}, the gain A_t and every
 // epilogue in FP64, and may store P_{t|t} in FP32. The mean-only smoother (kf_smooth_means)
-// replaces the smoother step by one N x N matrix-vector product per step over kept gain factors.
+// replaces the smoother step by one N x N matrix-vector product per step over kept gain factors;
+// kf_smooth_assoc regroups the smoother as an associative scan over time.
 #include "kf_internal.h"
 #include "arena.h"
 #include "../../include/kfmeg.h"
