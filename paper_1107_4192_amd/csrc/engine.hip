@@ -50,6 +50,8 @@ struct kf_plan {
     double* XQ = nullptr;                   // X Q (m x N): X (P + Q) = X P + X Q
     // filter workspace
     double *Bm = nullptr, *Cm = nullptr, *S = nullptr, *Lis = nullptr, *e = nullptr, *w = nullptr, *xw = nullptr;
+    double* Gmm = nullptr;                  // X C_{t-1}^T (m x m) for the recursive update of B
+    double* Bck = nullptr;                  // checkpointed store: B_t at every segment start (t % stride == 0)
     float* Cm32 = nullptr;
     double* partial = nullptr;
     size_t partial_elems = 0;
@@ -220,13 +222,18 @@ size_t factor_bytes(int64_t N, int64_t m, int64_t T) {
     return 8 * (size_t)T * ((size_t)m * ldN + (size_t)m * ldm + (size_t)ldm);
 }
 
+// B_t (m x N) kept at every segment start of a checkpointed store.
+size_t bck_bytes(int64_t N, int64_t m, int64_t T, int stride) {
+    return stride > 1 ? 8 * (size_t)(T / stride + 1) * (size_t)m * round_up(N, 16) : 0;
+}
+
 // np: gain batches in flight (np scratch sets W, Li and np + 1 gain sets).
 size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int gb, int np = 1) {
     const int64_t ldN = round_up(N, 16), ldm = round_up(m, 16);
     const size_t NN = (size_t)N * ldN;
     size_t b = 0;
     b += 8 * (2 * NN + 2 * (size_t)m * ldN + (size_t)m * ldm + 2 * (size_t)N);   // Q, P0, X, XQ, R, x0
-    b += 8 * (2 * (size_t)m * ldN + 2 * (size_t)m * ldm + 3 * (size_t)N + 64);
+    b += 8 * (2 * (size_t)m * ldN + 3 * (size_t)m * ldm + 3 * (size_t)N + 64);
     b += 8 * (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);                 // split-K partials
     const size_t sets = (size_t)np + 1;
     b += 8 * ((2 * (size_t)np + sets) * (size_t)gb + 2) * NN;                // W, Li per stream, A per set; Ps x2
@@ -253,12 +260,27 @@ kf_status status_check(kf_plan* p, const char* phase) {
     return KF_OK;
 }
 
+// How filter step t obtains B_t = X P_{t|t-1}. With F = I, P_{t|t-1} = P_{t-1|t-1} + Q (eqn7) and
+// P_{t-1|t-1} = P_{t-1|t-2} - C_{t-1}^T C_{t-1} (the update after eqn10), so
+//     B_t = B_{t-1} + X Q - (X C_{t-1}^T) C_{t-1},
+// 4 m^2 N flops instead of 2 m N^2. The full product is taken every kBRefresh steps (and
+// always with a general F), which bounds the drift of the recursion. A recomputed segment of a
+// checkpointed store starts from the B_t kept at its first step, so that it reproduces the
+// forward pass bit for bit.
+constexpr int64_t kBRefresh = 16;
+enum BMode { B_FULL, B_RECUR, B_KEPT };
+
+BMode b_mode(const kf_plan* p, int64_t t) { return (p->hasF || t % kBRefresh == 0) ? B_FULL : B_RECUR; }
+
 // One covariance step of the filter from P_prev = P_{t-1|t-1} (or P0) to P_t; with `y`, also the mean.
-// Pout32 (optional) receives a float32 copy of P_t.
+// Pout32 (optional) receives a float32 copy of P_t. `keep_b`: a checkpointed forward pass keeps
+// B_t at segment starts.
 kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* Pout64,
-                          float* Pout32, double* diag_out, const double* y, double* x_out_row) {
+                          float* Pout32, double* diag_out, const double* y, double* x_out_row,
+                          BMode bmode, bool keep_b) {
     const int N = (int)p->N, m = (int)p->m;
     hipStream_t s = p->stream;
+    const size_t mN = (size_t)m * p->ldN;
     // P_pred = P_prev + Q (F = I, never formed) or F P_prev F^T + Q (formed as F (P_prev F^T) + Q)
     const double* Ppred = nullptr;
     if (p->hasF) {
@@ -268,7 +290,31 @@ kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* 
     }
     // B = X P_pred: with F = I, X P_prev + X Q. Float64 in both precisions: the gain and the
     // mean depend on it through S^{-1}, where rounding is amplified by cond(S).
-    {
+    if (bmode == B_KEPT) {
+        HIPCK(hipMemcpyAsync(p->Bm, p->Bck + (size_t)(t / p->stride) * mN, mN * 8, hipMemcpyDeviceToDevice, s));
+    } else if (bmode == B_RECUR) {
+        {   // G = X C_{t-1}^T
+            GemmProblem g;
+            g.M = m; g.N = m; g.K = N;
+            g.A = p->X; g.lda = p->ldN;
+            g.B = p->Cm; g.ldb = p->ldN; g.flags = G_TB;
+            g.C = p->Gmm; g.ldc = p->ldm;
+            g.ksplit = std::max(1, std::min(32, N / 128));
+            g.partial = p->partial;
+            HIPCK(gemm1(Dt::F64, g, s));
+        }
+        {   // B_t = B_{t-1} + X Q - G C_{t-1}   (in place)
+            GemmProblem g;
+            g.M = m; g.N = N; g.K = m;
+            g.A = p->Gmm; g.lda = p->ldm;
+            g.B = p->Cm; g.ldb = p->ldN;
+            g.alpha = -1.0;
+            g.Cin = p->Bm; g.ldcin = p->ldN; g.beta = 1.0;
+            g.Cin2 = p->XQ; g.ldcin2 = p->ldN; g.gamma = 1.0;
+            g.C = p->Bm; g.ldc = p->ldN;
+            HIPCK(gemm1(Dt::F64, g, s));
+        }
+    } else {
         GemmProblem g;
         g.M = m; g.N = N; g.K = N;
         g.ksplit = 4;
@@ -279,6 +325,8 @@ kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* 
         g.B = Ppred ? Ppred : Pprev64; g.ldb = p->ldN; g.flags = G_TB;   // P symmetric: read row-contiguous
         HIPCK(gemm1(Dt::F64, g, s));
     }
+    if (keep_b && p->stride > 1 && t % p->stride == 0)
+        HIPCK(hipMemcpyAsync(p->Bck + (size_t)(t / p->stride) * mN, p->Bm, mN * 8, hipMemcpyDeviceToDevice, s));
     // S = B X^T + R
     {
         GemmProblem g;
@@ -502,7 +550,8 @@ size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt) {
     const int64_t ldN = round_up(N, 16);
     const int stride = o.checkpoint_stride > 0 ? o.checkpoint_stride : 1;
     return workspace_bytes(N, m, o.precision == KF_MIXED, o.store_fp32, stride, kMaxBatch) +
-           store_bytes(N, ldN, T, o.store_fp32, stride) + (o.keep_gain_factors ? factor_bytes(N, m, T) : 0);
+           store_bytes(N, ldN, T, o.store_fp32, stride) + bck_bytes(N, m, T, stride) +
+           (o.keep_gain_factors ? factor_bytes(N, m, T) : 0);
 }
 
 }  // extern "C"
@@ -552,6 +601,7 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     int np = arena ? 1 : kMaxProd;          // serving plans keep one gain batch in flight
     auto need = [&](int st, int gb) {
         return workspace_bytes(N, m, mix, p->store32, st, gb, np) + store_bytes(N, p->ldN, T_max, p->store32, st) +
+               bck_bytes(N, m, T_max, st) +
                fac;
     };
     // Prefer storing every P_{t|t}; give up the second gain batch in flight, then gain
@@ -584,7 +634,8 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
 #define ALLOC(ptr, n)                        \
     if ((st = alloc(p, &(ptr), (n))) != KF_OK) return fail(st);
     ALLOC(p->X, mN); ALLOC(p->XQ, mN); ALLOC(p->Q, NN); ALLOC(p->R, mm); ALLOC(p->x0, (size_t)N); ALLOC(p->P0, NN);
-    ALLOC(p->Bm, mN); ALLOC(p->Cm, mN); ALLOC(p->S, mm); ALLOC(p->Lis, mm);
+    ALLOC(p->Bm, mN); ALLOC(p->Cm, mN); ALLOC(p->S, mm); ALLOC(p->Lis, mm); ALLOC(p->Gmm, mm);
+    if (stride > 1) ALLOC(p->Bck, (size_t)(T_max / stride + 1) * mN);
     ALLOC(p->e, (size_t)m); ALLOC(p->w, (size_t)m); ALLOC(p->xw, (size_t)N);
     p->partial_elems = (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);
     ALLOC(p->partial, p->partial_elems);
@@ -683,7 +734,8 @@ size_t plan_bytes_ex(int64_t N, int64_t m, int64_t T, const kf_options* opt, int
     const int64_t ldN = round_up(N, 16);
     const int stride = o.checkpoint_stride > 0 ? o.checkpoint_stride : 1;
     return workspace_bytes(N, m, o.precision == KF_MIXED, o.store_fp32, stride, gb) +
-           store_bytes(N, ldN, T, o.store_fp32, stride) + (o.keep_gain_factors ? factor_bytes(N, m, T) : 0);
+           store_bytes(N, ldN, T, o.store_fp32, stride) + bck_bytes(N, m, T, stride) +
+           (o.keep_gain_factors ? factor_bytes(N, m, T) : 0);
 }
 
 }  // namespace kfmeg
@@ -735,9 +787,9 @@ static kf_status filter_impl(kf_plan* p, int64_t B, int64_t T, const double* Y, 
         if (!slot64(p) && kept(p, t, T)) out32 = static_cast<float*>(slot_ptr(p, slot_of(p, t, T)));
         double* diag = Pdiag ? Pdiag + t * N : nullptr;
         if (B == 1) {
-            TRY(filter_cov_step(p, t, prev64, out64, out32, diag, Y + t * m, x_filt + t * N));
+            TRY(filter_cov_step(p, t, prev64, out64, out32, diag, Y + t * m, x_filt + t * N, b_mode(p, t), true));
         } else {
-            TRY(filter_cov_step(p, t, prev64, out64, out32, diag, nullptr, nullptr));
+            TRY(filter_cov_step(p, t, prev64, out64, out32, diag, nullptr, nullptr, b_mode(p, t), true));
             const double* xprev = t == 0 ? p->Xb0 : x_filt + (t - 1) * N;
             TRY(filter_mean_batch(p, B, xprev, t == 0 ? p->ldN : T * N, Y + t * m, T * m, x_filt + t * N, T * N));
         }
@@ -800,7 +852,8 @@ kf_status recompute_segment(kf_plan* p, int64_t t0, int64_t t1, int64_t T) {
         double* out64 = p->Pw[(t - t0 + 1) & 1];
         void* segslot = static_cast<char*>(p->seg) + (size_t)(t - t0) * slot_elems(p) * esz;
         float* out32 = s32 ? static_cast<float*>(segslot) : nullptr;
-        TRY(filter_cov_step(p, t, prev64, out64, out32, nullptr, nullptr, nullptr));
+        const BMode bm = (t == t0 && b_mode(p, t) == B_RECUR) ? B_KEPT : b_mode(p, t);
+        TRY(filter_cov_step(p, t, prev64, out64, out32, nullptr, nullptr, nullptr, bm, false));
         if (!s32) HIPCK(hipMemcpyAsync(segslot, out64, slot_elems(p) * 8, hipMemcpyDeviceToDevice, s));
         prev64 = out64;
     }
