@@ -43,7 +43,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL = "gemm_kernel<double, 1, 4>"    # the smoother's N x N x N products, float64 path
+KERNEL = "gemm_kernel<double, 1, *>"    # the smoother's N x N x N products, float64 path (NT and NN layouts)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_nxn_f64_paper_N5124_traffic.json")
 GEMM_SOURCE = os.path.join(ROOT, "paper_1107_4192_amd", "csrc", "gemm.hip")
 

@@ -890,22 +890,22 @@ kf_status gain_batch(kf_plan* p, int set, int q, int count, const int64_t* ts, c
         steps[b] = (int)ts[b] + 1;
     }
     HIPCK(chol_inv_batch(N, Wq, ld, Liq, ld, count, p->dstatus, W_PPRED, steps, s));
-    // A_t = P_t Li^T Li. H = P_t Li^T goes into W (L is not needed any more); Li is then
-    // transposed in place so that both products read their second operand row-contiguous.
+    // A_t = P_t Li^T Li. H = P_t Li^T goes into W (L is not needed any more). The first product
+    // takes Li as a transposed operand (upper triangular in (k, l)), the second as stored (lower
+    // triangular in (k, j)); each skips the zero triangle of its K range.
     GemmProblem g[kMaxBatch], h[kMaxBatch];
     for (int b = 0; b < count; ++b) {
         g[b].M = N; g[b].N = N; g[b].K = N;    // H = P_t F^T Li^T   (B(l,k) = Li[k][l], zero for l > k)
         g[b].A = p->hasF ? p->Ab[set][b] : P64[b]; g[b].lda = ld;
         g[b].B = Liq[b]; g[b].ldb = ld; g[b].flags = G_TB | G_BUPPER;
         g[b].C = Wq[b]; g[b].ldc = ld;
-        h[b].M = N; h[b].N = N; h[b].K = N;    // A_t = H Li     (B(k,j) = Li[k][j] = LiT[j][k])
+        h[b].M = N; h[b].N = N; h[b].K = N;    // A_t = H Li     (B(k,j) = Li[k][j], zero for k < j)
         h[b].A = Wq[b]; h[b].lda = ld;
-        h[b].B = Liq[b]; h[b].ldb = ld; h[b].flags = G_TB | G_BLOWER;
+        h[b].B = Liq[b]; h[b].ldb = ld; h[b].flags = G_BLOWER;
         h[b].C = p->Ab[set][b]; h[b].ldc = ld;
         if (mixed(p)) { h[b].C32 = p->A32[set][b]; h[b].ldc32 = ld; }
     }
     TRY(big_group(p, Dt::F64, g, count, (double)count * N * N * N, s));
-    for (int b = 0; b < count; ++b) HIPCK(transpose_inplace(Liq[b], ld, N, s));
     TRY(big_group(p, Dt::F64, h, count, (double)count * N * N * N, s));
     return KF_OK;
 }

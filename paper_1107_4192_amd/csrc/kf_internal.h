@@ -125,8 +125,6 @@ hipError_t add_diag(double* A, int64_t lda, int n, double v, hipStream_t s);
 hipError_t zero2d(int rows, int cols, double* dst, int64_t ldd, hipStream_t s);
 // scan n values for NaN / Inf; sets *flag = 1 if any
 hipError_t nonfinite_scan(const double* v, int64_t n, int* flag, hipStream_t s);
-// transpose a square matrix in place
-hipError_t transpose_inplace(double* A, int64_t lda, int n, hipStream_t s);
 // store diag of a square double matrix to out
 hipError_t diag_copy(const double* A, int64_t lda, int n, double* out, hipStream_t s);
 

@@ -202,30 +202,6 @@ __global__ void diag_kernel(const double* A, int64_t lda, int n, double* out) {
     if (i < n) out[i] = A[(int64_t)i * lda + i];
 }
 
-// In-place transpose of a square n x n matrix: one workgroup per 64 x 64 tile pair
-// (bi >= bj), both tiles staged through LDS and written back swapped.
-constexpr int TT = 64;
-__global__ __launch_bounds__(256) void transpose_inplace_kernel(double* A, int64_t lda, int n, int tiles) {
-    __shared__ double t0[TT][TT + 1];
-    __shared__ double t1[TT][TT + 1];
-    int bi = (int)((sqrtf(8.0f * blockIdx.x + 1.0f) - 1.0f) * 0.5f);
-    while ((bi + 1) * (bi + 2) / 2 <= (int)blockIdx.x) ++bi;
-    while (bi * (bi + 1) / 2 > (int)blockIdx.x) --bi;
-    const int bj = blockIdx.x - bi * (bi + 1) / 2;
-    const int i0 = bi * TT, j0 = bj * TT;
-    for (int idx = threadIdx.x; idx < TT * TT; idx += 256) {
-        const int r = idx / TT, c = idx % TT;
-        if (i0 + r < n && j0 + c < n) t0[r][c] = A[(int64_t)(i0 + r) * lda + j0 + c];
-        if (j0 + r < n && i0 + c < n) t1[r][c] = A[(int64_t)(j0 + r) * lda + i0 + c];
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < TT * TT; idx += 256) {
-        const int r = idx / TT, c = idx % TT;
-        if (i0 + r < n && j0 + c < n) A[(int64_t)(i0 + r) * lda + j0 + c] = t1[c][r];
-        if (bi != bj && j0 + r < n && i0 + c < n) A[(int64_t)(j0 + r) * lda + i0 + c] = t0[c][r];
-    }
-}
-
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + TPB - 1) / TPB, 65536)); }
 
 dim3 grid2d(int rows, int cols) {
@@ -366,11 +342,6 @@ hipError_t nonfinite_scan(const double* v, int64_t n, int* flag, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t transpose_inplace(double* A, int64_t lda, int n, hipStream_t s) {
-    const int t = (n + TT - 1) / TT;
-    hipLaunchKernelGGL(transpose_inplace_kernel, dim3(t * (t + 1) / 2), dim3(256), 0, s, A, lda, n, t);
-    return hipGetLastError();
-}
 
 hipError_t diag_copy(const double* A, int64_t lda, int n, double* out, hipStream_t s) {
     hipLaunchKernelGGL(diag_kernel, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, A, lda, n, out);

@@ -64,14 +64,15 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, bench_log: str | None =
     fcopy = max(f[COPY_KERNEL]) * 1024.0
     wcopy = max(w[COPY_KERNEL]) * 1024.0
     ffac, wfac = COPY_BYTES / fcopy, COPY_BYTES / wcopy
-    name = next(k for k in f if kernel in k)
-    fk = [v * 1024.0 * ffac for v in f[name]]
-    wk = [v * 1024.0 * wfac for v in w[name]]
+    # every instantiation whose name contains `kernel` (e.g. one per operand layout)
+    names = sorted(k for k in f if kernel in k)
+    fk = [v * 1024.0 * ffac for k in names for v in f[k]]
+    wk = [v * 1024.0 * wfac for k in names for v in w.get(k, [])]
     n = min(len(fk), len(wk))
     per = [fk[i] + wk[i] for i in range(n)]
     src = os.path.join(HERE, "csrc", "gemm.hip")
     return {
-        "kernel": name,
+        "kernel": " + ".join(names),
         "dispatches": n,
         "fetch_scale": ffac,
         "write_scale": wfac,
