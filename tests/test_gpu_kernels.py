@@ -144,7 +144,8 @@ def _spd(n, seed, cond=1e3):
     return (A + A.T) / 2
 
 
-@pytest.mark.parametrize("n", [1, 2, 17, 63, 64, 65, 127, 128, 129, 200, 306, 500])
+@pytest.mark.parametrize("n", [1, 2, 17, 63, 64, 65, 127, 128, 129, 200, 306, 500,
+                               1024, 1025, 1300, 2100])   # one, two and three 1024-column outer blocks
 def test_chol_inv(n):
     A = _spd(n, n)
     # the strict upper triangle is never read: fill it with garbage
@@ -158,12 +159,12 @@ def test_chol_inv(n):
     assert np.abs(Li @ Lref - np.eye(n)).max() <= 1e-11 * max(1, n) ** 0.5 * 30
 
 
-def test_chol_inv_reports_first_bad_pivot():
-    n = 150
+@pytest.mark.parametrize("n,row", [(150, 100), (1300, 1100)])
+def test_chol_inv_reports_first_bad_pivot(n, row):
     A = _spd(n, 3, cond=10)
-    A[100, 100] = -1.0
+    A[row, row] = -1.0
     W = torch.tensor(A, device="cuda")
     with pytest.raises(kfmeg.KFError) as ei:
         F.kfd_chol_inv(W)
     assert ei.value.status == kfmeg.KF_ENOTPD
-    assert "pivot row 100" in str(ei.value)
+    assert f"pivot row {row}" in str(ei.value)
