@@ -860,10 +860,10 @@ kf_status recompute_segment(kf_plan* p, int64_t t0, int64_t t1, int64_t T) {
     return KF_OK;
 }
 
-// Smoother gains for a batch of steps (eqn11): A_t = P_{t|t} P_{t+1|t}^{-1} for each
-// t = ts[b], formed as G = Li P_t, A_t = G^T Li with L Li = chol(P_t + Q), into gain set
-// `set`. The steps are independent given the stored P_{t|t}, so every launch covers the
-// whole batch.
+// Smoother gains for a batch of steps (eqn11): A_t = P_{t|t} F^T P_{t+1|t}^{-1} for each
+// t = ts[b], formed as H = P_t F^T Li^T, A_t = H Li with L Li = chol(P_{t+1|t}), into gain
+// set `set` (H stays in the stream's W buffers). The steps are independent given the stored
+// P_{t|t}, so every launch covers the whole batch.
 kf_status gain_batch(kf_plan* p, int set, int q, int count, const int64_t* ts, const void* const* Pt,
                      const bool* is32, hipStream_t s) {
     double* const* Wq = p->W[q];
