@@ -7,21 +7,18 @@
 // A_t = P_{t|t} P_{t+1|t}^{-1} = (Li P_{t|t})^T Li. Li is obtained by solving
 // L Z = I in the same right-looking sweep as the factorisation.
 //
-// Three-level blocking keeps the O(n^3) work in large MFMA products with a long
+// Two-level blocking keeps the O(n^3) work in large MFMA products with a long
 // K dimension:
-//   for each 1024-column outer block [C0, R3):
-//     for each 256-column panel [c0, r2) of it:
-//       for each 64-column block k of the panel:
-//         1. one workgroup per matrix factors the diagonal block in LDS and inverts
-//            it (L_kk, Li_kk), flagging a non-positive or non-finite pivot;
-//         2. L_{>k,k} = A_{>k,k} Li_kk^T  and  Z_{k,<k} = Li_kk Z_{k,<k}
-//         3. inside the panel only: A_{>k,(k,r2)} -= L_{>k,k} L_{(k,r2),k}^T and
-//            Z_{(k,r2),<=k} -= L_{(k,r2),k} Z_{k,<=k}
-//       4. the rest of the outer block, K = 256: A_{>=r2,[r2,R3)} -= L_{>=r2,P} L_{[r2,R3),P}^T
-//          and Z_{[r2,R3),<r2} -= L_{[r2,R3),P} Z_{P,<r2}  (P = the panel)
-//     5. trailing, K = 1024:  A_{>=R3,>=R3} -= L_{>=R3,O} L_{>=R3,O}^T  and
-//        Z_{>=R3,<R3} -= L_{>=R3,O} Z_{O,<R3}  (O = the outer block)
-// Steps 2-5 are each one grouped GEMM launch over the whole batch, so the
+//   for each 256-column panel K:
+//     for each 64-column block k of the panel:
+//       1. one workgroup per matrix factors the diagonal block in LDS and inverts
+//          it (L_kk, Li_kk), flagging a non-positive or non-finite pivot;
+//       2. L_{>k,k} = A_{>k,k} Li_kk^T  and  Z_{k,<k} = Li_kk Z_{k,<k}
+//       3. inside the panel only: A_{>k,(k,K]} -= L_{>k,k} L_{(k,K],k}^T and
+//          Z_{(k,K],<=k} -= L_{(k,K],k} Z_{k,<=k}
+//     4. trailing, K = 256:  A_{>K,>K} -= L_{>K,K} L_{>K,K}^T  and
+//        Z_{>K,<=K} -= L_{>K,K} Z_{K,<=K}
+// Steps 2-4 are each one grouped GEMM launch over the whole batch, so the
 // latency of the sequential sweep is shared by every matrix of the batch.
 #include "kf_internal.h"
 
@@ -30,8 +27,7 @@ namespace kfmeg {
 namespace {
 
 constexpr int NB = 64;      // diagonal block
-constexpr int NB2 = 256;    // panel
-constexpr int NB3 = 1024;   // outer block (K of the trailing update)
+constexpr int NB2 = 256;    // panel (K of the trailing update)
 constexpr int NTD = 256;
 
 struct DiagBatch {
@@ -130,110 +126,81 @@ hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z
         if ((e = zero2d(n, n, Z[b], ldz, s)) != hipSuccess) return e;
     auto w = [&](int b, int i, int j) { return W[b] + (int64_t)i * ldw + j; };
     auto z = [&](int b, int i, int j) { return Z[b] + (int64_t)i * ldz + j; };
-    for (int C0 = 0; C0 < n; C0 += NB3) {
-        const int R3 = C0 + (n - C0 < NB3 ? n - C0 : NB3);
-        for (int c0 = C0; c0 < R3; c0 += NB2) {
-            const int r2 = c0 + (R3 - c0 < NB2 ? R3 - c0 : NB2);
-            for (int k0 = c0; k0 < r2; k0 += NB) {
-                const int kb = r2 - k0 < NB ? r2 - k0 : NB;
-                const int r = k0 + kb;
-                DiagBatch db;
-                for (int b = 0; b < count; ++b) {
-                    db.W[b] = w(b, k0, k0);
-                    db.Z[b] = z(b, k0, k0);
-                    db.step[b] = steps ? steps[b] : 0;
-                }
-                hipLaunchKernelGGL(potrf_inv_diag, dim3(count), dim3(NTD), 0, s, db, ldw, ldz, kb, status, which, k0);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int c0 = 0; c0 < n; c0 += NB2) {
+        const int r2 = c0 + (n - c0 < NB2 ? n - c0 : NB2);
+        for (int k0 = c0; k0 < r2; k0 += NB) {
+            const int kb = r2 - k0 < NB ? r2 - k0 : NB;
+            const int r = k0 + kb;
+            DiagBatch db;
+            for (int b = 0; b < count; ++b) {
+                db.W[b] = w(b, k0, k0);
+                db.Z[b] = z(b, k0, k0);
+                db.step[b] = steps ? steps[b] : 0;
+            }
+            hipLaunchKernelGGL(potrf_inv_diag, dim3(count), dim3(NTD), 0, s, db, ldw, ldz, kb, status, which, k0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
 
-                GemmProblem pr[kMaxGroup];
-                int np = 0;
-                for (int b = 0; b < count; ++b) {
-                    if (r < n) {              // L_{>k,k} = A_{>k,k} Li_kk^T   (in place, one column tile)
-                        GemmProblem p;
-                        p.M = n - r; p.N = kb; p.K = kb;
-                        p.A = w(b, r, k0); p.lda = ldw;
-                        p.B = z(b, k0, k0); p.ldb = ldz; p.flags = G_TB | G_BUPPER;
-                        p.C = w(b, r, k0); p.ldc = ldw;
-                        pr[np++] = p;
-                    }
-                    if (k0 > 0) {             // Z_{k,<k} = Li_kk Z_{k,<k}   (in place, one row tile)
-                        GemmProblem p;
-                        p.M = kb; p.N = k0; p.K = kb;
-                        p.A = z(b, k0, k0); p.lda = ldz; p.flags = G_ALOWER;
-                        p.B = z(b, k0, 0); p.ldb = ldz;
-                        p.C = z(b, k0, 0); p.ldc = ldz;
-                        pr[np++] = p;
-                    }
+            GemmProblem pr[kMaxGroup];
+            int np = 0;
+            for (int b = 0; b < count; ++b) {
+                if (r < n) {              // L_{>k,k} = A_{>k,k} Li_kk^T   (in place, one column tile)
+                    GemmProblem p;
+                    p.M = n - r; p.N = kb; p.K = kb;
+                    p.A = w(b, r, k0); p.lda = ldw;
+                    p.B = z(b, k0, k0); p.ldb = ldz; p.flags = G_TB | G_BUPPER;
+                    p.C = w(b, r, k0); p.ldc = ldw;
+                    pr[np++] = p;
                 }
-                if (np && (e = gemm_launch(Dt::F64, pr, np, s)) != hipSuccess) return e;
-                if (r < r2) {                 // updates inside the panel
-                    np = 0;
-                    for (int b = 0; b < count; ++b) {
-                        GemmProblem t1, t2;
-                        t1.M = n - r; t1.N = r2 - r; t1.K = kb;
-                        t1.A = w(b, r, k0); t1.lda = ldw;
-                        t1.B = w(b, r, k0); t1.ldb = ldw; t1.flags = G_TB;
-                        t1.alpha = -1.0; t1.beta = 1.0;
-                        t1.Cin = w(b, r, r); t1.ldcin = ldw;
-                        t1.C = w(b, r, r); t1.ldc = ldw;
-                        t2.M = r2 - r; t2.N = r; t2.K = kb;
-                        t2.A = w(b, r, k0); t2.lda = ldw;
-                        t2.B = z(b, k0, 0); t2.ldb = ldz;
-                        t2.alpha = -1.0; t2.beta = 1.0;
-                        t2.Cin = z(b, r, 0); t2.ldcin = ldz;
-                        t2.C = z(b, r, 0); t2.ldc = ldz;
-                        pr[np++] = t1;
-                        pr[np++] = t2;
-                    }
-                    if ((e = gemm_launch(Dt::F64, pr, np, s)) != hipSuccess) return e;
+                if (k0 > 0) {             // Z_{k,<k} = Li_kk Z_{k,<k}   (in place, one row tile)
+                    GemmProblem p;
+                    p.M = kb; p.N = k0; p.K = kb;
+                    p.A = z(b, k0, k0); p.lda = ldz; p.flags = G_ALOWER;
+                    p.B = z(b, k0, 0); p.ldb = ldz;
+                    p.C = z(b, k0, 0); p.ldc = ldz;
+                    pr[np++] = p;
                 }
             }
-            if (r2 < R3) {
-                // The rest of the outer block with K = this panel: its columns for every row below
-                // (lower tiles when the outer block reaches the last row), and the rows of Z that the
-                // outer block's next panels need.
-                GemmProblem pr[kMaxGroup];
-                int np = 0;
+            if (np && (e = gemm_launch(Dt::F64, pr, np, s)) != hipSuccess) return e;
+            if (r < r2) {                 // updates inside the panel
+                np = 0;
                 for (int b = 0; b < count; ++b) {
                     GemmProblem t1, t2;
-                    t1.M = n - r2; t1.N = R3 - r2; t1.K = r2 - c0;
-                    t1.A = w(b, r2, c0); t1.lda = ldw;
-                    t1.B = w(b, r2, c0); t1.ldb = ldw;
-                    t1.flags = G_TB | (R3 == n ? G_LOWER : 0);
+                    t1.M = n - r; t1.N = r2 - r; t1.K = kb;
+                    t1.A = w(b, r, k0); t1.lda = ldw;
+                    t1.B = w(b, r, k0); t1.ldb = ldw; t1.flags = G_TB;
                     t1.alpha = -1.0; t1.beta = 1.0;
-                    t1.Cin = w(b, r2, r2); t1.ldcin = ldw;
-                    t1.C = w(b, r2, r2); t1.ldc = ldw;
-                    t2.M = R3 - r2; t2.N = r2; t2.K = r2 - c0;
-                    t2.A = w(b, r2, c0); t2.lda = ldw;
-                    t2.B = z(b, c0, 0); t2.ldb = ldz;
+                    t1.Cin = w(b, r, r); t1.ldcin = ldw;
+                    t1.C = w(b, r, r); t1.ldc = ldw;
+                    t2.M = r2 - r; t2.N = r; t2.K = kb;
+                    t2.A = w(b, r, k0); t2.lda = ldw;
+                    t2.B = z(b, k0, 0); t2.ldb = ldz;
                     t2.alpha = -1.0; t2.beta = 1.0;
-                    t2.Cin = z(b, r2, 0); t2.ldcin = ldz;
-                    t2.C = z(b, r2, 0); t2.ldc = ldz;
+                    t2.Cin = z(b, r, 0); t2.ldcin = ldz;
+                    t2.C = z(b, r, 0); t2.ldc = ldz;
                     pr[np++] = t1;
                     pr[np++] = t2;
                 }
                 if ((e = gemm_launch(Dt::F64, pr, np, s)) != hipSuccess) return e;
             }
         }
-        if (R3 < n) {                         // trailing update with K = the outer block
+        if (r2 < n) {                     // trailing update with K = the panel width
             GemmProblem pr[kMaxGroup];
             int np = 0;
             for (int b = 0; b < count; ++b) {
                 GemmProblem t1, t2;
-                t1.M = n - R3; t1.N = n - R3; t1.K = R3 - C0;
-                t1.A = w(b, R3, C0); t1.lda = ldw;
-                t1.B = w(b, R3, C0); t1.ldb = ldw;
+                t1.M = n - r2; t1.N = n - r2; t1.K = r2 - c0;
+                t1.A = w(b, r2, c0); t1.lda = ldw;
+                t1.B = w(b, r2, c0); t1.ldb = ldw;
                 t1.flags = G_TB | G_LOWER;
                 t1.alpha = -1.0; t1.beta = 1.0;
-                t1.Cin = w(b, R3, R3); t1.ldcin = ldw;
-                t1.C = w(b, R3, R3); t1.ldc = ldw;
-                t2.M = n - R3; t2.N = R3; t2.K = R3 - C0;
-                t2.A = w(b, R3, C0); t2.lda = ldw;
-                t2.B = z(b, C0, 0); t2.ldb = ldz;
+                t1.Cin = w(b, r2, r2); t1.ldcin = ldw;
+                t1.C = w(b, r2, r2); t1.ldc = ldw;
+                t2.M = n - r2; t2.N = r2; t2.K = r2 - c0;
+                t2.A = w(b, r2, c0); t2.lda = ldw;
+                t2.B = z(b, c0, 0); t2.ldb = ldz;
                 t2.alpha = -1.0; t2.beta = 1.0;
-                t2.Cin = z(b, R3, 0); t2.ldcin = ldz;
-                t2.C = z(b, R3, 0); t2.ldc = ldz;
+                t2.Cin = z(b, r2, 0); t2.ldcin = ldz;
+                t2.C = z(b, r2, 0); t2.ldc = ldz;
                 pr[np++] = t1;
                 pr[np++] = t2;
             }

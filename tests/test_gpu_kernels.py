@@ -145,7 +145,7 @@ def _spd(n, seed, cond=1e3):
 
 
 @pytest.mark.parametrize("n", [1, 2, 17, 63, 64, 65, 127, 128, 129, 200, 306, 500,
-                               1024, 1025, 1300, 2100])   # one, two and three 1024-column outer blocks
+                               1024, 1025, 1300, 2100])   # up to nine 256-column panels
 def test_chol_inv(n):
     A = _spd(n, n)
     # the strict upper triangle is never read: fill it with garbage
