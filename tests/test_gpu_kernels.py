@@ -159,7 +159,7 @@ def test_chol_inv(n):
     assert np.abs(Li @ Lref - np.eye(n)).max() <= 1e-11 * max(1, n) ** 0.5 * 30
 
 
-@pytest.mark.parametrize("n,row", [(150, 100), (1300, 1100)])
+@pytest.mark.parametrize("n,row", [(150, 100), (150, 101), (1300, 1100), (70, 64), (70, 65)])
 def test_chol_inv_reports_first_bad_pivot(n, row):
     A = _spd(n, 3, cond=10)
     A[row, row] = -1.0
