@@ -1219,6 +1219,7 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
     std::vector<char> ezero(T, 0);               // suffix already contains step T-1: E = 0
     ezero[T - 1] = 1;
 
+    p->T_done = 0;                                       // the stored P_{t|t} are overwritten below
     HIPCK(hipMemsetAsync(p->dstatus, 0, 4 * sizeof(int), s));
     HIPCK(zero2d(1, n, zero, N, s));
     HIPCK(hipMemcpyAsync(xs + (T - 1) * N, xf + (T - 1) * N, N * 8, hipMemcpyDeviceToDevice, s));
@@ -1330,7 +1331,6 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
             HIPCK(hipMemcpy2DAsync(Pfull + t * N * N, N * 8, L[t], ld * 8, N * 8, N, hipMemcpyDeviceToDevice, s));
     }
     const kf_status st = sync_and_check(p, "kf_smooth_assoc");
-    p->T_done = 0;                                       // the stored P_{t|t} are gone
     if (st == KF_OK && p->prof) TRY(collect_profile(p));
     return st;
 }
