@@ -119,16 +119,11 @@ __global__ __launch_bounds__(NTD) void potrf_inv_diag(DiagBatch B, int64_t ldw, 
 }  // namespace
 
 hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z, int64_t ldz, int count,
-                          int* status, int which, const int* steps, hipStream_t s, const double* const* P,
-                          const double* Q) {
-    if (count < 1 || count > kMaxBatch || (P && !Q)) return hipErrorInvalidValue;
+                          int* status, int which, const int* steps, hipStream_t s) {
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
     hipError_t e;
-    for (int b = 0; b < count; ++b) {
+    for (int b = 0; b < count; ++b)
         if ((e = zero2d(n, n, Z[b], ldz, s)) != hipSuccess) return e;
-        if (P && (e = axpby3(n, n < NB2 ? n : NB2, W[b], false, ldw, P[b], false, ldw, Q, false, ldw, 1.0, nullptr,
-                             false, 0, 0.0, s)) != hipSuccess)
-            return e;
-    }
     auto w = [&](int b, int i, int j) { return W[b] + (int64_t)i * ldw + j; };
     auto z = [&](int b, int i, int j) { return Z[b] + (int64_t)i * ldz + j; };
     for (int c0 = 0; c0 < n; c0 += NB2) {
@@ -199,10 +194,6 @@ hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z
                 t1.flags = G_TB | G_LOWER;
                 t1.alpha = -1.0; t1.beta = 1.0;
                 t1.Cin = w(b, r2, r2); t1.ldcin = ldw;
-                if (P && c0 == 0) {           // the first trailing update starts from P + Q
-                    t1.Cin = P[b] + (int64_t)r2 * ldw + r2;
-                    t1.Cin2 = Q + (int64_t)r2 * ldw + r2; t1.ldcin2 = ldw; t1.gamma = 1.0;
-                }
                 t1.C = w(b, r2, r2); t1.ldc = ldw;
                 t2.M = n - r2; t2.N = r2; t2.K = r2 - c0;
                 t2.A = w(b, r2, c0); t2.lda = ldw;

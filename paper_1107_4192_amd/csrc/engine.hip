@@ -882,12 +882,14 @@ kf_status gain_batch(kf_plan* p, int set, int q, int count, const int64_t* ts, c
             // G_t = P_t F^T (kept in A_t's buffer until A_t overwrites it); W = F G_t + Q (eqn7)
             HIPCK(dense_sparse_t(p->F, P64[b], ld, p->Ab[set][b], ld, s));
             HIPCK(spmm_rows(p->F, p->Ab[set][b], ld, 1.0, p->Q, ld, 1.0, nullptr, 0, 0.0, Wq[b], false, ld, s));
+        } else {
+            // W = P_t + Q  (= P_{t+1|t}, eqn7)
+            HIPCK(axpby3(N, N, Wq[b], false, ld, P64[b], false, ld, p->Q, false, ld, 1.0, nullptr, false, 0, 0.0,
+                         s));
         }
         steps[b] = (int)ts[b] + 1;
     }
-    // F = I: the factorisation starts from W = P_t + Q (= P_{t+1|t}, eqn7) without forming it first
-    HIPCK(chol_inv_batch(N, Wq, ld, Liq, ld, count, p->dstatus, W_PPRED, steps, s, p->hasF ? nullptr : P64,
-                         p->hasF ? nullptr : p->Q));
+    HIPCK(chol_inv_batch(N, Wq, ld, Liq, ld, count, p->dstatus, W_PPRED, steps, s));
     // A_t = P_t Li^T Li. H = P_t Li^T goes into W (L is not needed any more). The first product
     // takes Li as a transposed operand (upper triangular in (k, l)), the second as stored (lower
     // triangular in (k, j)); each skips the zero triangle of its K range.

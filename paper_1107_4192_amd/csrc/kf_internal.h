@@ -79,12 +79,8 @@ enum Which : int { W_S = 1, W_PPRED = 2, W_MNE = 3 };
 hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, int* status,
                     int which, int step, hipStream_t s);
 // The same for `count` <= kMaxBatch independent matrices of one size, sharing every launch.
-// With `P` (count matrices) and `Q`, W[b] starts as P[b] + Q, formed on the way (the first
-// panel's columns by one elementwise pass, the rest by the first trailing update's epilogue)
-// instead of being read from W; P and Q (leading dimension ldw) are not modified.
 hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z, int64_t ldz, int count,
-                          int* status, int which, const int* steps, hipStream_t s,
-                          const double* const* P = nullptr, const double* Q = nullptr);
+                          int* status, int which, const int* steps, hipStream_t s);
 
 // ---------------------------------------------------------------- vector / elementwise kernels
 // e = y - X x  (X: m x N, ld ldx)
