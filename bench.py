@@ -17,11 +17,15 @@ Besides the contract's JSON fields the line carries:
                 workload, and its difference from the full smoother's means;
   batched       eight data sets of the same model through one covariance pass
                 (kf_filter_batch + kf_smooth_batch), in data-set time-steps/s;
+  assoc         kf_smooth_assoc (the smoother as an associative scan over time) against
+                kf_smooth: smoother seconds on the tiny workload at two horizons and on this
+                workload, and its difference from the step-by-step smoother;
   serving       p50/p99 job latency and throughput of the continuous-batching server on a
                 Poisson stream of jobs of mixed N, m, T, against the same jobs run one at a
                 time in FP64.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--T 200] [--no-cpu] [--no-mixed] [--no-serving]
+                       [--no-extra] [--workload paper|free|serving]
 """
 from __future__ import annotations
 
