@@ -55,3 +55,34 @@ def test_product_path_has_no_oracle_import():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libkfmeg.so not built")
+def test_argument_errors_before_any_launch():
+    # Empty or negative sizes and null pointers are rejected on the host, before any device
+    # call, with KF_EINVAL and a message; the calls below never reach the GPU.
+    lib = ctypes.CDLL(LIB)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    lib.kf_create.argtypes = [ctypes.POINTER(vp), i64, i64, i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.kf_create.restype = ctypes.c_int
+    lib.kf_last_error.argtypes = [vp]
+    lib.kf_last_error.restype = ctypes.c_char_p
+    lib.mne_solve.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp]
+    lib.mne_solve.restype = ctypes.c_int
+    lib.kf_filter.argtypes = [vp, i64, vp, vp, vp]
+    lib.kf_filter.restype = ctypes.c_int
+    lib.kf_smooth_assoc.argtypes = [vp, vp, vp, vp]
+    lib.kf_smooth_assoc.restype = ctypes.c_int
+    KF_EINVAL = 1
+    dummy = ctypes.c_void_p(16)          # never dereferenced: the sizes are rejected first
+    plan = vp()
+    for N, m, T in ((0, 3, 4), (5, 0, 4), (5, 3, 0), (-1, 3, 4)):
+        st = lib.kf_create(ctypes.byref(plan), N, m, T, dummy, dummy, dummy, dummy, dummy, None, None)
+        assert st == KF_EINVAL and not plan.value
+        assert b"sizes" in lib.kf_last_error(None)
+    st = lib.kf_create(ctypes.byref(plan), 5, 3, 4, None, dummy, dummy, dummy, dummy, None, None)
+    assert st == KF_EINVAL and b"null" in lib.kf_last_error(None)
+    assert lib.mne_solve(5, 3, 0, dummy, dummy, dummy, dummy, dummy, None) == KF_EINVAL
+    assert lib.mne_solve(5, 3, 2, None, dummy, dummy, dummy, dummy, None) == KF_EINVAL
+    assert lib.kf_filter(None, 3, dummy, dummy, None) == KF_EINVAL
+    assert lib.kf_smooth_assoc(None, dummy, None, None) == KF_EINVAL
