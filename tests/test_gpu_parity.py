@@ -77,6 +77,19 @@ def test_tiny_workload_full_parity():
     assert all(np.array_equal(P, P.T) for P in filt)
 
 
+def test_long_horizon_parity():
+    """T=120: the filter's B_t is updated recursively between full products every 16 steps;
+    over seven refresh periods the outputs still meet the float64 tolerance, in both precisions."""
+    p = synth.tiny(T=120)
+    ref = oracle_run(p)
+    res, _ = gpu_run(p)
+    errs = check_all(res, None, ref, TOL64)
+    print("T=120 fp64 errors", errs)
+    res, _ = gpu_run(p, precision=kfmeg.KF_MIXED, store_fp32=True)
+    errs = check_all(res, None, ref, TOLMIX)
+    print("T=120 mixed errors", errs)
+
+
 def test_tiny_workload_mixed_precision():
     p = synth.tiny()
     res, _ = gpu_run(p, precision=kfmeg.KF_MIXED, store_fp32=True)
