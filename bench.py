@@ -12,7 +12,9 @@ Besides the contract's JSON fields the line carries:
   cpu_baseline  the FP64 oracle timed on this host on a bounded sample (the first 10 steps
                 of the same workload at full N: filter 10 steps + smoother 9 steps);
   mixed         the same workload in mixed precision (FP32 MFMA bulk, FP64 factorisations,
-                FP32 store): its rate, speedup over FP64 and its error against the FP64 path;
+                FP32 store): its rate, speedup over FP64, its error against the FP64 path, and its
+                pass against the bound of its FP64 work at the FP64 peak plus its FP32 work at
+                the FP32 peak;
   mean_only     kf_filter + kf_smooth_means (smoothed means without P_{t|T}) on the same
                 workload, and its difference from the full smoother's means;
   batched       eight data sets of the same model through one covariance pass
@@ -20,6 +22,7 @@ Besides the contract's JSON fields the line carries:
   assoc         kf_smooth_assoc (the smoother as an associative scan over time) against
                 kf_smooth: smoother seconds on the tiny workload at two horizons and on this
                 workload, and its difference from the step-by-step smoother;
+  transfers     host <-> device time of one job's inputs and outputs (outside the timed region);
   serving       p50/p99 job latency and throughput of the continuous-batching server on a
                 Poisson stream of jobs of mixed N, m, T, against the same jobs run one at a
                 time in FP64.
@@ -148,6 +151,47 @@ def path_roofline(p, ms_pass):
     achieved = flops / (ms_pass * 1e-3)
     return {"flops_per_pass": flops, "achieved": achieved / 1e12, "frac": achieved / PEAK_F64,
             "unit": "TFLOP/s"}
+
+
+def mixed_roofline(p, ms_pass):
+    """Mixed-precision bound of one pass: the float64 work (Cholesky of S and of P_{t+1|t}, the
+    two gain products) at the FP64 peak plus the float32 work (X P, S, C^T C; eqn13's M = A_t D
+    and P_t + M A_t^T) at the FP32 peak, against the measured pass."""
+    N, m, T = p.N, p.m, p.T
+    f64 = T * m ** 3 / 3.0 + (T - 1) * (N ** 3 / 3.0 + 2.0 * N ** 3)
+    f32 = T * (3.0 * m * N * N + 3.0 * m * m * N) + (T - 1) * 3.0 * N ** 3
+    bound_ms = (f64 / PEAK_F64 + f32 / PEAK_F32) * 1e3
+    return {"f64_flops_per_pass": f64, "f32_flops_per_pass": f32, "bound_ms_per_pass": bound_ms,
+            "measured_ms_per_pass": ms_pass, "frac": bound_ms / ms_pass}
+
+
+def transfer_times(p):
+    """Host <-> device time of one job's inputs (X, Q, R, x0, P0, Y) and outputs (x_{t|T} and the
+    diagonals of P_{t|T}) through pinned host buffers; outside the timed region of `value`."""
+    import numpy as np
+    import torch
+
+    host = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory() for a in (p.X, p.Q, p.R, p.x0, p.P0, p.Y)]
+    nbytes_in = sum(h.numel() * h.element_size() for h in host)
+    out_dev = [torch.empty((p.T, p.N), dtype=torch.float64, device="cuda") for _ in range(2)]
+    out_host = [torch.empty((p.T, p.N), dtype=torch.float64).pin_memory() for _ in range(2)]
+    nbytes_out = sum(h.numel() * h.element_size() for h in out_host)
+    best_in = best_out = 1e30
+    for _ in range(3):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        dev = [h.to("cuda", non_blocking=True) for h in host]
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        for d, h in zip(out_dev, out_host):
+            h.copy_(d, non_blocking=True)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        best_in, best_out = min(best_in, b - a), min(best_out, c - b)
+        del dev
+    return {"h2d_s": best_in, "h2d_bytes": nbytes_in, "d2h_s": best_out, "d2h_bytes": nbytes_out,
+            "what": "pinned host buffers; inputs X, Q, R, x0, P0, Y and outputs x_{t|T}, diag P_{t|T} of one "
+                    "job; not part of the timed region"}
 
 
 def run_mean_only(p, steps, xs_ref):
@@ -444,7 +488,9 @@ def main():
         line["mixed"] = {"value": vmx, "unit": "time-steps/s", "speedup_vs_fp64": vmx / value,
                          "eps_x_smooth_vs_fp64_path": ex, "eps_diagP_smooth_vs_fp64_path": ed,
                          "store": "fp32", "filter_s_per_pass": rmx["t_filter"],
-                         "smoother_s_per_pass": rmx["t_smooth"]}
+                         "smoother_s_per_pass": rmx["t_smooth"],
+                         "roofline": mixed_roofline(p, rmx["elapsed"] / max(1, args.steps) * 1e3)}
+    line["transfers"] = transfer_times(p)
     if not args.no_extra:
         line["mean_only"] = run_mean_only(p, max(1, args.steps), r64["x_smooth"])
         line["batched"] = run_batched(p, 8, 1)
