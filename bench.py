@@ -4,17 +4,23 @@ One benchmark "step" is one pass of the whole hot path -- kf_filter over T time
 steps followed by kf_smooth -- over the paper-scale synthetic workload (N=5124
 fixed-orientation sources, m=306 sensors, T=200 steps, float64 throughout),
 with all inputs resident in HBM before the timed region. The reported value is
-time-steps per second: T * steps / elapsed.
+time-steps per second: T * steps / elapsed; ms_per_step is the time of one time
+step (ms_per_pass / T), ms_per_pass that of one whole pass.
 
 Besides the contract's JSON fields the line carries:
-  roofline      the smoother's N x N x N products (the dominant kernel, f64 MFMA), timed
-                live with HIP events around each launch during the timed region;
-  cpu_baseline  the FP64 oracle timed on this host on a bounded sample (the first 10 steps
-                of the same workload at full N: filter 10 steps + smoother 9 steps);
+  roofline      the smoother's float64 N x N x N products (the dominant kernel,
+                gemm_kernel<double, 1, *>), event-timed live during the timed region on the
+                streams they run on, one event pair per dispatch; `isolated` is the same
+                products in one extra pass serialised onto one stream (each runs alone,
+                gemm_kernel<double, 3, *>); `path` is the whole pass against the FP64 peak;
+  cpu_baseline  the FP64 oracle timed on this host on a bounded sample (the first 16 steps of
+                the same workload at full N: filter 16 steps + smoother 15 steps);
+  accuracy      the float64 and mixed-precision GPU paths against that same oracle run (same
+                inputs, same 16-step horizon): normwise and element-wise errors per result;
   mixed         the same workload in mixed precision (FP32 MFMA bulk, FP64 factorisations,
-                FP32 store): its rate, speedup over FP64, its error against the FP64 path, and its
-                pass against the bound of its FP64 work at the FP64 peak plus its FP32 work at
-                the FP32 peak;
+                FP32 store): its rate, speedup over FP64, its error against the oracle (from
+                `accuracy`) and against the FP64 path at T=200, and its pass against the bound of
+                its FP64 work at the FP64 peak plus its FP32 work at the FP32 peak;
   mean_only     kf_filter + kf_smooth_means (smoothed means without P_{t|T}) on the same
                 workload, and its difference from the full smoother's means;
   batched       eight data sets of the same model through one covariance pass
@@ -23,12 +29,16 @@ Besides the contract's JSON fields the line carries:
                 kf_smooth: smoother seconds on the tiny workload at two horizons and on this
                 workload, and its difference from the step-by-step smoother;
   transfers     host <-> device time of one job's inputs and outputs (outside the timed region);
+  free_orientation  N=15372 (5124 sites x 3), m=306, T=100, mixed precision, float32 store: the
+                whole store in HBM and again under a budget that forces checkpoint-and-recompute
+                (outputs must agree bit for bit);
   serving       p50/p99 job latency and throughput of the continuous-batching server on a
                 Poisson stream of jobs of mixed N, m, T, against the same jobs run one at a
-                time in FP64.
+                time in FP64; `constrained` runs a second stream under a 40 GiB budget that an
+                N=8196, T=150 job cannot fit without checkpointing.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--T 200] [--no-cpu] [--no-mixed] [--no-serving]
-                       [--no-extra] [--workload paper|free|serving]
+                       [--no-extra] [--no-free] [--workload paper|free|serving]
 """
 from __future__ import annotations
 
@@ -80,8 +90,27 @@ def calibration_copy():
     log("calibration copy: 3 x 256 MiB device-to-device")
 
 
-def cpu_baseline(p, T_sample=10):
-    """Time the FP64 oracle (as it stands) on a bounded sample of the same workload."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def truncated(p, T):
+    """The same workload cut to its first T steps (same X, Q, R, x0, P0 and data)."""
+    import copy
+    q = copy.copy(p)
+    q.Y = p.Y[:T].copy()
+    return q
+
+
+def cpu_baseline(p, T_sample=16):
+    """Time the FP64 oracle (as it stands) on a bounded sample of the same workload; its outputs
+    also serve as the reference of the accuracy leg."""
     import numpy as np
     import oracle
     try:
@@ -89,16 +118,56 @@ def cpu_baseline(p, T_sample=10):
         cores = max((i.get("num_threads", 1) for i in threadpool_info()), default=os.cpu_count())
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
+    q = truncated(p, T_sample)
     t0 = time.perf_counter()
-    xf, Pf, _ = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, p.Y[:T_sample])
-    oracle.rts_smooth(xf, Pf, p.Q)
+    xf, Pf, dPf = oracle.kf_filter(q.X, q.Q, q.R, q.x0, q.P0, q.Y)
+    xs, _, dPs = oracle.rts_smooth(xf, Pf, q.Q)
     dt = time.perf_counter() - t0
-    return {"value": T_sample / dt, "unit": "time-steps/s", "cores": int(cores), "kind": "oracle",
+    base = {"value": T_sample / dt, "unit": "time-steps/s", "cores": int(cores), "kind": "oracle",
+            "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
             "sample": f"first {T_sample} steps of the N={p.N}, m={p.m} workload at full size: "
                       f"filter {T_sample} steps + smoother {T_sample - 1} steps, {dt:.1f} s"}
+    return base, (q, xf, dPf, xs, dPs)
 
 
-def run_gpu(p, precision, steps, warmup, store_fp32=False, profile=False):
+def accuracy(ref):
+    """Float64 and mixed-precision GPU runs on the oracle's own inputs and horizon: normwise per step
+    (max over steps: ||x^ - x|| / max ||x||, ||d^ - d||_inf / ||d||_inf) and element-wise
+    (|g - w| / (|w| + 1e-3 max_i |w_t,i|)) errors of x_{t|t}, diag P_{t|t}, x_{t|T}, diag P_{t|T}."""
+    import numpy as np
+    import torch
+    from paper_1107_4192_amd import kfmeg
+
+    q, xf, dPf, xs, dPs = ref
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+    def nx(g, w):
+        return float(np.linalg.norm(g - w, axis=1).max() / np.linalg.norm(w, axis=1).max())
+
+    def nd(g, w):
+        return float((np.abs(g - w).max(axis=1) / np.abs(w).max(axis=1)).max())
+
+    def el(g, w):
+        return float((np.abs(g - w) / (np.abs(w) + 1e-3 * np.abs(w).max(axis=1, keepdims=True))).max())
+
+    out = {"horizon": q.T, "what": f"GPU against the FP64 oracle on the first {q.T} steps of the workload "
+                                   "(both sides run the same truncated problem)"}
+    for label, opt in (("fp64", {}), ("mixed_fp32_store", {"precision": kfmeg.KF_MIXED, "store_fp32": True})):
+        ks = kfmeg.KalmanSmoother(dev(q.X), dev(q.Q), dev(q.R), dev(q.x0), dev(q.P0), T_max=q.T, **opt)
+        try:
+            r = ks.run(dev(q.Y))
+        finally:
+            ks.close()
+        g = {k: getattr(r, k).cpu().numpy() for k in ("x_filt", "Pdiag_filt", "x_smooth", "Pdiag_smooth")}
+        out[label] = {"eps_x_filt": nx(g["x_filt"], xf), "eps_diagP_filt": nd(g["Pdiag_filt"], dPf),
+                      "eps_x_smooth": nx(g["x_smooth"], xs), "eps_diagP_smooth": nd(g["Pdiag_smooth"], dPs),
+                      "elem_x_smooth": el(g["x_smooth"], xs), "elem_diagP_smooth": el(g["Pdiag_smooth"], dPs),
+                      "elem_diagP_filt": el(g["Pdiag_filt"], dPf)}
+        log(f"accuracy {label}: " + ", ".join(f"{k} {v:.1e}" for k, v in out[label].items()))
+    return out
+
+
+def run_gpu(p, precision, steps, warmup, store_fp32=False, profile=False, isolated=False):
     import numpy as np
     import torch
     from paper_1107_4192_amd import kfmeg
@@ -139,6 +208,18 @@ def run_gpu(p, precision, steps, warmup, store_fp32=False, profile=False):
     prof = kfmeg.kf_get_profile(ks.plan) if profile else None
     out = {"elapsed": elapsed, "t_filter": t_filter / steps, "t_smooth": t_smooth / steps, "prof": prof,
            "x_smooth": xs.clone(), "d_smooth": ds.clone()}
+    if isolated:
+        # one more pass, outside the timed region, with the smoother serialised onto one stream:
+        # each product runs alone (a separately named kernel instantiation)
+        kfmeg.kf_set_profiling(ks.plan, 2)
+        kfmeg.kf_filter(ks.plan, Y, xf, df)
+        a = time.perf_counter()
+        kfmeg.kf_smooth(ks.plan, xs, ds, None)
+        torch.cuda.synchronize()
+        out["isolated_smoother_s"] = time.perf_counter() - a
+        out["isolated_prof"] = kfmeg.kf_get_profile(ks.plan)
+        kfmeg.kf_set_profiling(ks.plan, 0)
+        log(f"isolated (serialised) smoother pass: {out['isolated_smoother_s']:.3f} s")
     ks.close()
     return out
 
@@ -307,22 +388,24 @@ def run_batched(p, B, steps):
 
 
 def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(102, 204, 306),
-                T_range=(20, 60), max_active=4, budget_gib=0.0):
+                T_range=(20, 60), max_active=4, budget_gib=0.0, plan=None):
     """Serving form: Poisson arrivals of filter+smoother jobs of mixed shapes, mixed precision
-    with float32 stores, continuously batched; against the same jobs one at a time in FP64."""
+    with float32 stores, continuously batched; against the same jobs one at a time in FP64.
+    `plan` replaces the drawn stream with an explicit job list (arrival_s, N, m, T, seed)."""
     import numpy as np
     import torch
     from paper_1107_4192_amd import kfmeg, synth
 
-    plan = synth.serving_jobs(seed=seed, n_jobs=n_jobs, rate_per_s=rate, N_choices=N_choices,
-                              m_choices=m_choices, T_range=T_range)
+    if plan is None:
+        plan = synth.serving_jobs(seed=seed, n_jobs=n_jobs, rate_per_s=rate, N_choices=N_choices,
+                                  m_choices=m_choices, T_range=T_range)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     t0 = time.perf_counter()
     jobs = []
     for j in plan:
         p = synth.custom(j["seed"], j["N"], j["m"], j["T"])
         jobs.append((j, tuple(dev(a) for a in (p.X, p.Q, p.R, p.x0, p.P0, p.Y))))
-    log(f"serving: {n_jobs} jobs generated in {time.perf_counter() - t0:.1f} s")
+    log(f"serving: {len(jobs)} jobs generated in {time.perf_counter() - t0:.1f} s")
     # continuous batching, mixed precision + float32 store
     srv = kfmeg.Server(hbm_budget_bytes=int(budget_gib * 2 ** 30), max_active=max_active,
                        precision=kfmeg.KF_MIXED, store_fp32=True)
@@ -338,7 +421,8 @@ def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(
     st = srv.stats()
     infos = [srv.info(i) for i in ids]
     srv.close()
-    log(f"serving: {st['completed']} jobs, p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms")
+    log(f"serving: {st['completed']} jobs, p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms, "
+        f"{st['checkpointed']} checkpointed")
     # baseline: the same jobs one at a time in plain FP64
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -350,15 +434,27 @@ def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(
     seq = time.perf_counter() - t0
     steps = sum(j["T"] for j, _ in jobs)
     log(f"serving: sequential FP64 {seq:.1f} s")
-    return {"workload": f"{n_jobs} jobs, Poisson arrivals {rate}/s, N in {list(N_choices)}, "
-                        f"m in {list(m_choices)}, T in {list(T_range)}; mixed precision, float32 store"
-                        + (f", HBM budget {budget_gib:g} GiB" if budget_gib else ""),
+    shapes = sorted({(j["N"], j["m"]) for j in plan})
+    return {"workload": f"{len(jobs)} jobs, N x m in {shapes}, T in [{min(j['T'] for j in plan)}, "
+                        f"{max(j['T'] for j in plan)}], arrivals over {plan[-1]['arrival_s']:.1f} s; mixed "
+                        "precision, float32 store" + (f", HBM budget {budget_gib:g} GiB" if budget_gib else ""),
             "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "jobs_per_s": st["jobs_per_s"],
             "steps_per_s": st["steps_per_s"], "max_concurrent": st["max_concurrent"],
             "checkpointed": st["checkpointed"], "peak_gib": st["peak_bytes"] / 2 ** 30,
             "sequential_fp64_steps_per_s": steps / seq,
             "throughput_speedup_vs_sequential_fp64": st["steps_per_s"] / (steps / seq),
-            "mean_queue_ms": float(np.mean([i["queued_ms"] for i in infos]))}
+            "mean_queue_ms": float(np.mean([i["queued_ms"] for i in infos])),
+            "checkpoint_strides": [i["checkpoint_stride"] for i in infos]}
+
+
+# A stream that a 40 GiB server cannot hold without checkpointing: the N=8196, T=150 job alone needs
+# 40 GB of float32 covariance store plus its workspace, so it is admitted with a checkpointed store.
+CONSTRAINED_JOBS = [
+    {"job": 0, "arrival_s": 0.0, "N": 8196, "m": 306, "T": 150, "seed": 9100},
+    {"job": 1, "arrival_s": 0.4, "N": 2000, "m": 102, "T": 60, "seed": 9101},
+    {"job": 2, "arrival_s": 0.8, "N": 5124, "m": 204, "T": 40, "seed": 9102},
+    {"job": 3, "arrival_s": 1.2, "N": 2000, "m": 306, "T": 50, "seed": 9103},
+]
 
 
 def run_free(T=100, budget_gib=64.0):
@@ -410,10 +506,11 @@ def main():
     ap.add_argument("--T", type=int, default=200)
     ap.add_argument("--N", type=int, default=5124)
     ap.add_argument("--m", type=int, default=306)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and the accuracy leg")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 256 MiB copy first (HBM counter scale)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-free", action="store_true", help="skip the free-orientation leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the mean-only, batched and associative-scan legs")
     ap.add_argument("--workload", choices=("paper", "free", "serving"), default="paper",
                     help="free: the free-orientation N=15372 workload only (full store and checkpointed); "
@@ -445,11 +542,13 @@ def main():
     p = synth.paper(T=args.T, N=args.N, m=args.m)
     log(f"workload N={p.N} m={p.m} T={p.T} generated in {time.perf_counter() - t0:.1f} s")
 
-    r64 = run_gpu(p, kfmeg.KF_FP64, args.steps, args.warmup, profile=True)
+    r64 = run_gpu(p, kfmeg.KF_FP64, args.steps, args.warmup, profile=True, isolated=True)
     value = p.T * args.steps / r64["elapsed"]
     ms_pass = r64["elapsed"] / args.steps * 1e3
     kms, kflops, launches = r64["prof"]
     achieved = kflops / (kms * 1e-3) if kms > 0 else 0.0
+    ims, iflops, ilaunches = r64["isolated_prof"]
+    iachieved = iflops / (ims * 1e-3) if ims > 0 else 0.0
     line = {
         "metric": "KF+FIS time-steps/sec at N=5124, m=306 (FP64 vs mixed); p50/p99 job latency",
         "value": value,
@@ -457,7 +556,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_pass,
+        "ms_per_step": ms_pass / p.T,
+        "ms_per_pass": ms_pass,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -465,18 +565,30 @@ def main():
         "data": "synthetic (seeded dipole lead field on a spherical shell, Gaussian-kernel Q, 3 sinusoidal patches, 5 dB)",
         "config": {"workload": "paper-scale fixed orientation: N=5124 sources, m=306 sensors, T=200, float64",
                    "N": p.N, "m": p.m, "T": p.T, "precision": "fp64", "store": "fp64",
+                   "step": "one benchmark step = one pass of kf_filter over T time steps + kf_smooth",
                    "filter_s_per_pass": r64["t_filter"], "smoother_s_per_pass": r64["t_smooth"]},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_F64 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_F64, "traffic": measured_traffic(kflops / max(launches, 1)),
-                     "kernel": KERNEL + " (smoother N x N x N products: A_t factors and eqn13)",
+                     "kernel": KERNEL + " (smoother N x N x N products: A_t factors and eqn13), overlapped "
+                               "with the gain streams as in the timed passes",
                      "launches": launches, "avg_launch_ms": kms / max(launches, 1),
                      "flops_per_launch": kflops / max(launches, 1),
+                     # the same products in one extra smoother pass serialised onto one stream
+                     "isolated": {"kernel": "gemm_kernel<double, 3, *>", "launches": ilaunches,
+                                  "avg_launch_ms": ims / max(ilaunches, 1),
+                                  "flops_per_launch": iflops / max(ilaunches, 1),
+                                  "achieved": iachieved / 1e12, "frac": iachieved / PEAK_F64,
+                                  "smoother_s": r64["isolated_smoother_s"]},
                      # the whole filter + smoother pass against the same peak: algorithmic flops
                      # (rank-m filter, N^3/3 Cholesky, 2 N^3 gain, 3 N^3 eqn13; no explicit inverse)
-                     # over the timed wall clock; the smoother's two gain streams share the GPU with
-                     # the back-recursion, which stretches each launch's event-timed duration
+                     # over the timed wall clock
                      "path": path_roofline(p, ms_pass)},
     }
+    ref = None
+    if not args.no_cpu:
+        line["cpu_baseline"], ref = cpu_baseline(p)
+        log(f"cpu baseline: {line['cpu_baseline']['value']:.3f} time-steps/s on {line['cpu_baseline']['cores']} threads")
+        line["accuracy"] = accuracy(ref)
     if not args.no_mixed:
         import numpy as np
         rmx = run_gpu(p, kfmeg.KF_MIXED, max(1, args.steps), 1, store_fp32=True, profile=True)
@@ -490,15 +602,21 @@ def main():
                          "store": "fp32", "filter_s_per_pass": rmx["t_filter"],
                          "smoother_s_per_pass": rmx["t_smooth"],
                          "roofline": mixed_roofline(p, rmx["elapsed"] / max(1, args.steps) * 1e3)}
+        if "accuracy" in line:
+            acc = line["accuracy"]["mixed_fp32_store"]
+            line["mixed"].update({"eps_x_smooth_vs_oracle": acc["eps_x_smooth"],
+                                  "eps_diagP_smooth_vs_oracle": acc["eps_diagP_smooth"],
+                                  "oracle_horizon": line["accuracy"]["horizon"]})
     line["transfers"] = transfer_times(p)
     if not args.no_extra:
         line["mean_only"] = run_mean_only(p, max(1, args.steps), r64["x_smooth"])
         line["batched"] = run_batched(p, 8, 1)
         line["assoc"] = run_assoc(p, r64["t_smooth"], r64["x_smooth"], r64["d_smooth"])
+    if not args.no_free:
+        line["free_orientation"] = run_free()
     if not args.no_serving:
         line["serving"] = run_serving()
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(p)
+        line["serving"]["constrained"] = run_serving(plan=CONSTRAINED_JOBS, max_active=4, budget_gib=40.0)
     print(json.dumps(line), flush=True)
 
 

@@ -225,11 +225,17 @@ const char* kf_last_error(const kf_plan* plan);
 /*
  * Profiling of the smoother's N x N x N products (the triangular products
  * that form A_t, eqn11, and the two products of eqn13), which carry most of
- * the arithmetic. With profiling on, kf_smooth brackets each such launch with
- * a pair of HIP events on the plan's stream; kf_get_profile returns the summed
- * kernel time in ms, the summed algorithmic flops (N^3 for each triangular or
- * half-output product, 2 N^3 for the full one) and the number of launches
- * since profiling was last switched on. kf_set_profiling resets the totals.
+ * the arithmetic. With profiling on (on = 1), kf_smooth brackets each such
+ * launch with a pair of HIP events on the stream it runs on, the closing one
+ * recorded right after the product kernel (before any split reduction), so an
+ * event pair spans one dispatch; kf_get_profile returns the summed event time
+ * in ms, the summed algorithmic flops (N^3 for each triangular or half-output
+ * product, 2 N^3 for the full one) and the number of launches since profiling
+ * was last switched on. on = 2 also serialises the smoother onto the plan's
+ * stream (the gain batches no longer overlap the back-recursion), so that each
+ * product runs alone; its float64 products then run as a separately named
+ * kernel instantiation. on = 0 switches both off. kf_set_profiling resets the
+ * totals; KF_EINVAL for other values of on.
  */
 kf_status kf_set_profiling(kf_plan* plan, int on);
 kf_status kf_get_profile(const kf_plan* plan, double* kernel_ms, double* kernel_flops, int64_t* launches);
@@ -259,7 +265,11 @@ size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt);
  * kfs_submit enqueues a job and returns at once. All array arguments are device
  * pointers as in kf_create / kf_smooth and must stay valid until kfs_wait for
  * that job returns. x_smooth (T x N) and Pdiag_smooth (T x N, or NULL) receive
- * x_{t|T} and diag P_{t|T}.
+ * x_{t|T} and diag P_{t|T}. `stream` (a hipStream_t, NULL = the null stream) is the
+ * stream the caller wrote the inputs on: the job's work starts only after everything
+ * enqueued on it before the call has finished, so inputs produced by asynchronous GPU
+ * work are safe to pass. The outputs are complete when kfs_wait returns; KF_EHIP if
+ * the ordering event cannot be recorded.
  * kfs_wait blocks until the job is done and returns its status (KF_ENOTPD,
  * KF_ENOMEM if it can never fit the budget, ...); latency_ms = completion minus
  * submission.
@@ -284,7 +294,7 @@ typedef struct {
 kf_status kfs_create(kfs_server** out, size_t hbm_budget_bytes, int max_active, const kf_options* opt);
 kf_status kfs_submit(kfs_server* srv, int64_t N, int64_t m, int64_t T, const double* X, const double* Q,
                      const double* R, const double* x0, const double* P0, const double* Y,
-                     double* x_smooth, double* Pdiag_smooth, int64_t* job_id);
+                     double* x_smooth, double* Pdiag_smooth, void* stream, int64_t* job_id);
 kf_status kfs_wait(kfs_server* srv, int64_t job_id, double* latency_ms);
 kf_status kfs_cancel(kfs_server* srv, int64_t job_id);
 kf_status kfs_job_info(kfs_server* srv, int64_t job_id, int* done, int* checkpoint_stride,

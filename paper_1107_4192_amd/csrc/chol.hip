@@ -49,8 +49,8 @@ struct DiagBatch {
 // one FMA each. Column j of L (colbuf / sqrt(d_j)) is collected in LDS and written
 // out at the end. 1/sqrt(d_j) comes from the hardware estimate refined by two
 // Newton steps (accurate to a few ulp).
-__global__ __launch_bounds__(NTD) void potrf_inv_diag(DiagBatch B, int64_t ldw, int64_t ldz, int nb, int* status,
-                                                      int which, int row0) {
+__global__ __launch_bounds__(NTD) void potrf_inv_diag(DiagBatch B, int64_t ldw, int64_t ldz, int nb,
+                                                      DevStatus* status, int which, int row0) {
     __shared__ double colbuf[2][NB];
     __shared__ double urow[2][NB];
     __shared__ double piv[2];
@@ -107,19 +107,14 @@ __global__ __launch_bounds__(NTD) void potrf_inv_diag(DiagBatch B, int64_t ldw, 
             Z[(int64_t)i * ldz + c] = c <= i ? u[r] * invs[i] : 0.0;
         }
     }
-    if (tid == 0 && bad >= 0 && bad < nb && status) {
-        if (atomicCAS(&status[0], 0, 1) == 0) {
-            status[1] = which;
-            status[2] = B.step[blockIdx.x];
-            status[3] = row0 + bad;
-        }
-    }
+    if (tid == 0 && bad >= 0 && bad < nb && status)
+        atomicMin(&status->key, status_key(B.step[blockIdx.x], row0 + bad, which));
 }
 
 }  // namespace
 
 hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z, int64_t ldz, int count,
-                          int* status, int which, const int* steps, hipStream_t s) {
+                          DevStatus* status, int which, const int* steps, hipStream_t s) {
     if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
     hipError_t e;
     for (int b = 0; b < count; ++b)
@@ -210,8 +205,8 @@ hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z
     return hipSuccess;
 }
 
-hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, int* status, int which, int step,
-                    hipStream_t s) {
+hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, DevStatus* status, int which,
+                    int step, hipStream_t s) {
     return chol_inv_batch(n, &W, ldw, &Z, ldz, 1, status, which, &step, s);
 }
 

@@ -59,17 +59,17 @@ int kfd_gemm_tail(int dtype, int M, int N, int K, int flags, const void* A, int6
 int kfd_chol_inv(int n, double* W, int64_t ldw, double* Z, int64_t ldz, int* pivot_row, void* stream) {
     if (n <= 0 || !W || !Z || ldw < n || ldz < n) return 1;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int* dst = nullptr;
-    if (hipMalloc(&dst, 4 * sizeof(int)) != hipSuccess) return 4;
-    int h[4] = {0, 0, 0, 0};
-    hipError_t e = hipMemsetAsync(dst, 0, 4 * sizeof(int), s);
+    DevStatus* dst = nullptr;
+    if (hipMalloc(&dst, sizeof(DevStatus)) != hipSuccess) return 4;
+    DevStatus h{};
+    hipError_t e = status_clear(dst, s);
     if (e == hipSuccess) e = chol_inv(W, ldw, Z, ldz, n, dst, W_MNE, 0, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(h, dst, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, dst, sizeof h, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dst);
     if (e != hipSuccess) return 4;
-    if (h[0]) {
-        if (pivot_row) *pivot_row = h[3];
+    if (h.key != kStatusClear) {
+        if (pivot_row) *pivot_row = status_row(h.key);
         return 2;
     }
     return 0;

@@ -80,11 +80,12 @@ struct kf_plan {
     // P_t + M A_t^T, lower tiles), chosen once per plan
     TailSplit ts_m, ts_low;
     void* tail_ws = nullptr;
+    void* tail_ws64 = nullptr;              // mixed plan with a transition F: eqn13 runs in float64
     hipStream_t s2[kMaxProd] = {};
     hipEvent_t ev_start = nullptr, ev_gain[kMaxProd + 1] = {}, ev_chain[kMaxProd + 1] = {};
     // status
-    int* dstatus = nullptr;
-    int* hstatus = nullptr;
+    DevStatus* dstatus = nullptr;
+    DevStatus* hstatus = nullptr;
     int64_t T_done = 0;
     int64_t B_done = 1;           // data sets of the last filter call
     double* xf_last = nullptr;    // caller's x_filt of the last filter call (for the smoother)
@@ -105,8 +106,10 @@ struct kf_plan {
     double *Fg = nullptr, *Fp = nullptr, *xp = nullptr;   // P F^T, F P F^T + Q, F x
     double* Ub = nullptr;                   // B x ldN: F applied to B means
     std::string err;
-    // profiling of the smoother's N x N x N products (event pairs around each launch)
+    // profiling of the smoother's N x N x N products (event pairs around each launch); `serial`
+    // runs the smoother's gain batches on the plan's stream too, so that each product runs alone
     bool prof = false;
+    bool serial = false;
     std::vector<hipEvent_t> ev;
     std::vector<double> ev_flops;
     size_t ev_used = 0;
@@ -248,12 +251,15 @@ size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int
 }
 
 kf_status status_check(kf_plan* p, const char* phase) {
-    if (p->hstatus[0]) {
-        const char* which = p->hstatus[1] == W_S ? "S_t = X P_{t|t-1} X^T + R"
-                          : p->hstatus[1] == W_PPRED ? "P_{t+1|t} = P_{t|t} + Q" : "X C X^T + R";
+    const unsigned long long k = p->hstatus->key;
+    if (k != kStatusClear) {
+        const int w = status_which(k);
+        const char* which = w == W_S ? "S_t = X P_{t|t-1} X^T + R"
+                          : w == W_PPRED ? (p->hasF ? "P_{t+1|t} = F P_{t|t} F^T + Q" : "P_{t+1|t} = P_{t|t} + Q")
+                                         : "X C X^T + R";
         char buf[256];
         snprintf(buf, sizeof buf, "%s: %s is not positive definite at step t=%d (pivot row %d)", phase, which,
-                 p->hstatus[2], p->hstatus[3]);
+                 status_step(k), status_row(k));
         p->err = buf;
         return KF_ENOTPD;
     }
@@ -484,7 +490,7 @@ kf_status smooth_mean_batch(kf_plan* p, int64_t B, const double* A, int64_t t, c
 }
 
 kf_status sync_and_check(kf_plan* p, const char* phase) {
-    HIPCK(hipMemcpyAsync(p->hstatus, p->dstatus, 4 * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+    HIPCK(hipMemcpyAsync(p->hstatus, p->dstatus, sizeof(DevStatus), hipMemcpyDeviceToHost, p->stream));
     HIPCK(hipStreamSynchronize(p->stream));
     return status_check(p, phase);
 }
@@ -492,7 +498,8 @@ kf_status sync_and_check(kf_plan* p, const char* phase) {
 // Launch a group of the smoother's N x N x N products (named instantiation), timed when profiling.
 kf_status big_group(kf_plan* p, Dt dt, GemmProblem* g, int count, double flops, hipStream_t st,
                     const TailSplit* ts = nullptr) {
-    for (int u = 0; u < count; ++u) g[u].flags |= mixed(p) ? G_NXN_MIXED : G_NXN;
+    const int name = p->serial && dt == Dt::F64 ? G_NXN_SERIAL : mixed(p) ? G_NXN_MIXED : G_NXN;
+    for (int u = 0; u < count; ++u) g[u].flags |= name;
     if (p->prof) {
         while (p->ev.size() < p->ev_used + 2) {
             hipEvent_t e;
@@ -501,10 +508,13 @@ kf_status big_group(kf_plan* p, Dt dt, GemmProblem* g, int count, double flops, 
         }
         HIPCK(hipEventRecord(p->ev[p->ev_used], st));
     }
-    if (ts && ts->k > 1 && p->tail_ws && count == 1) HIPCK(gemm_launch_tail(dt, g[0], *ts, p->tail_ws, st));
-    else HIPCK(gemm_launch(dt, g, count, st));
+    // The closing event is recorded right after the product kernel itself, before any split
+    // reduction, so that each event pair spans exactly one dispatch of the named kernel.
+    hipEvent_t done = p->prof ? p->ev[p->ev_used + 1] : nullptr;
+    void* ws = (dt == Dt::F64 && mixed(p)) ? p->tail_ws64 : p->tail_ws;
+    if (ts && ts->k > 1 && ws && count == 1) HIPCK(gemm_launch_tail(dt, g[0], *ts, ws, st, done));
+    else HIPCK(gemm_launch(dt, g, count, st, done));
     if (p->prof) {
-        HIPCK(hipEventRecord(p->ev[p->ev_used + 1], st));
         p->ev_flops.push_back(flops);
         p->ev_used += 2;
     }
@@ -605,8 +615,11 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
                fac;
     };
     // Prefer storing every P_{t|t}; give up the second gain batch in flight, then gain
-    // batching, before checkpointing.
+    // batching, before checkpointing. A short horizon needs no wider batch than its T - 1
+    // smoother steps, and a single batch (a 2-step first batch, then gb steps) no second stream.
     int gb = kMaxBatch;
+    while (gb > 1 && gb / 2 >= T_max - 1) gb /= 2;
+    if (T_max - 1 <= 2) np = 1;
     while (np > 1 && need(stride, gb) > budget) --np;
     while (gb > 1 && need(stride, gb) > budget) gb /= 2;
     if (p->opt.checkpoint_stride <= 0) {
@@ -639,7 +652,7 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     ALLOC(p->e, (size_t)m); ALLOC(p->w, (size_t)m); ALLOC(p->xw, (size_t)N);
     p->partial_elems = (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);
     ALLOC(p->partial, p->partial_elems);
-    ALLOC(p->dstatus, 4);
+    ALLOC(p->dstatus, 1);
     for (int b = 0; b < p->gbatch; ++b) {
         for (int q = 0; q < p->nprod; ++q) { ALLOC(p->W[q][b], NN); ALLOC(p->Li[q][b], NN); }
         for (int set = 0; set <= p->nprod; ++set) {
@@ -682,7 +695,7 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
         }
     }
 #undef ALLOC
-    if (hipHostMalloc(reinterpret_cast<void**>(&p->hstatus), 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->hstatus), sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
         p->err = "pinned host allocation failed";
         return fail(KF_ENOMEM);
     }
@@ -750,11 +763,11 @@ kf_status kf_create(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const do
 static kf_status filter_impl(kf_plan* p, int64_t B, int64_t T, const double* Y, double* x_filt, double* Pdiag) {
     hipStream_t s = p->stream;
     const int64_t N = p->N, m = p->m;
-    HIPCK(hipMemsetAsync(p->dstatus, 0, 4 * sizeof(int), s));
-    HIPCK(nonfinite_scan(Y, B * T * m, p->dstatus, s));
-    HIPCK(hipMemcpyAsync(p->hstatus, p->dstatus, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCK(status_clear(p->dstatus, s));
+    HIPCK(nonfinite_scan(Y, B * T * m, &p->dstatus->flag, s));
+    HIPCK(hipMemcpyAsync(p->hstatus, p->dstatus, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
-    if (p->hstatus[0]) {
+    if (p->hstatus->flag) {
         p->err = "kf_filter: Y holds a non-finite value";
         return KF_EINVAL;
     }
@@ -929,7 +942,10 @@ kf_status chain_step(kf_plan* p, int set, int b, int64_t t, const void* Pt, cons
         HIPCK(gemv_smooth(A, ld, xf + t * N, xpred, xs + (t + 1) * N, xs + t * N, N, s));
     }
     else TRY(smooth_mean_batch(p, p->B_done, A, t, xf, xs));
-    if (mixed(p)) {
+    // With a transition F the gain A_t has a large norm (F P_{t|t} F^T + Q is far worse
+    // conditioned than P_{t|t} + Q), so A_t D A_t^T forms a small result from large terms and
+    // float32 accumulation loses the stated accuracy: eqn13 then runs in float64 in both precisions.
+    if (mixed(p) && !p->hasF) {
         // D = P_{t+1|T} - P_t - Q in float32; M = A D; P_{t|T} = P_t + M A^T   (eqn13)
         if (p->hasF) {                      // D = P_{t+1|T} - F (P_t F^T) - Q
             HIPCK(dense_sparse_t(p->F, Pt64, ld, p->Fg, ld, s));
@@ -979,7 +995,7 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
     const bool s32 = p->store32;
     const size_t esz = s32 ? 4 : 8;
     const double* xf = p->xf_last;
-    HIPCK(hipMemsetAsync(p->dstatus, 0, 4 * sizeof(int), s));
+    HIPCK(status_clear(p->dstatus, s));
     // t = T-1: smoother = filter
     const void* PT = slot_ptr(p, slot_of(p, T - 1, T));
     if (s32) HIPCK(copy2d_r32((int)N, (int)N, p->Ps[(T - 1) & 1], ld, PT, !slot64(p), ld, s));
@@ -1001,7 +1017,7 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
         }
         return KF_OK;
     };
-    if (p->stride == 1) {
+    if (p->stride == 1 && !p->serial) {
         // Every P_{t|t} is stored: gains run one batch ahead on the side stream.
         struct Batch { int count; int64_t ts[kMaxBatch]; const void* Pt[kMaxBatch]; bool is32[kMaxBatch]; };
         std::vector<Batch> batches;
@@ -1042,8 +1058,8 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
             HIPCK(hipEventRecord(p->ev_chain[set], s));
         }
     } else {
-        // Checkpointed store: segments are recomputed into one buffer, so everything
-        // stays on the plan's stream.
+        // Checkpointed store (segments are recomputed into one buffer) or a serialised
+        // measurement pass: everything stays on the plan's stream.
         int64_t seg_lo = -1, seg_hi = -2;
         auto stored = [&](int64_t u) -> const void* {
             if (kept(p, u, T)) return slot_ptr(p, slot_of(p, u, T));
@@ -1220,7 +1236,7 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
     ezero[T - 1] = 1;
 
     p->T_done = 0;                                       // the stored P_{t|t} are overwritten below
-    HIPCK(hipMemsetAsync(p->dstatus, 0, 4 * sizeof(int), s));
+    HIPCK(status_clear(p->dstatus, s));
     HIPCK(zero2d(1, n, zero, N, s));
     HIPCK(hipMemcpyAsync(xs + (T - 1) * N, xf + (T - 1) * N, N * 8, hipMemcpyDeviceToDevice, s));
 
@@ -1463,6 +1479,10 @@ kf_status kf_set_transition(kf_plan* p, int64_t nnz, const int32_t* row_ptr, con
     for (void* a : p->fallocs) (void)hipFree(a);
     p->fallocs.clear();
     p->hasF = false;
+    if (mixed(p)) {                                 // the float64 eqn13 buffers lived in fallocs
+        p->Dm = p->Mm = nullptr;
+        p->tail_ws64 = nullptr;
+    }
     auto dev = [&](const void* src, size_t bytes) -> void* {
         void* d = nullptr;
         if (hipMalloc(&d, bytes) != hipSuccess) {
@@ -1477,7 +1497,17 @@ kf_status kf_set_transition(kf_plan* p, int64_t nnz, const int32_t* row_ptr, con
     void *a = dev(rp.data(), (N + 1) * 4), *b = dev(ci.data(), nnz * 4), *c = dev(v.data(), nnz * 8);
     void *d = dev(trp.data(), (N + 1) * 4), *e = dev(tci.data(), nnz * 4), *f = dev(tv.data(), nnz * 8);
     void *g = dev(nullptr, NN), *h = dev(nullptr, NN), *x = dev(nullptr, (size_t)p->ldN * 8);
-    if (!a || !b || !c || !d || !e || !f || !g || !h || !x) {
+    bool more = true;
+    if (mixed(p)) {                                 // eqn13 in float64 under F (see chain_step)
+        void *dm = dev(nullptr, NN), *mm = dev(nullptr, NN);
+        const size_t tb = tail_bytes(N, false);
+        void* tw = tb ? dev(nullptr, tb) : nullptr;
+        more = dm && mm && (tw || !tb);
+        p->Dm = static_cast<double*>(dm);
+        p->Mm = static_cast<double*>(mm);
+        p->tail_ws64 = tw;
+    }
+    if (!a || !b || !c || !d || !e || !f || !g || !h || !x || !more) {
         p->err = "kf_set_transition: device allocation failed";
         return KF_ENOMEM;
     }
@@ -1522,7 +1552,12 @@ kf_status kf_get_filtered_cov(kf_plan* p, int64_t t, double* P_out) {
 
 kf_status kf_set_profiling(kf_plan* p, int on) {
     if (!p) return KF_EINVAL;
+    if (on < 0 || on > 2) {
+        p->err = "kf_set_profiling: on must be 0, 1 or 2";
+        return KF_EINVAL;
+    }
     p->prof = on != 0;
+    p->serial = on == 2;
     p->prof_ms = 0.0;
     p->prof_flops = 0.0;
     p->prof_launches = 0;
@@ -1579,8 +1614,8 @@ kf_status mne_solve(int64_t N, int64_t m, int64_t T, const double* X, const doub
     kf_plan* p = &tmp;
     const int64_t ldm = round_up(m, 16), ldT = round_up(T, 16);
     double *G, *S, *Lis, *U, *V, *part;
-    int* status;
-    int hstat[4] = {0, 0, 0, 0};
+    DevStatus* status;
+    DevStatus hstat{};
     kf_status st = KF_OK;
     auto cleanup = [&](kf_status r) {
         for (void* a : tmp.allocs) (void)hipFree(a);
@@ -1596,10 +1631,10 @@ kf_status mne_solve(int64_t N, int64_t m, int64_t T, const double* X, const doub
     MALLOC(U, (size_t)m * ldT);
     MALLOC(V, (size_t)m * ldT);
     MALLOC(part, (size_t)32 * m * m);
-    MALLOC(status, 4);
+    MALLOC(status, 1);
 #undef MALLOC
     auto run = [&]() -> kf_status {
-        HIPCK(hipMemsetAsync(status, 0, 4 * sizeof(int), s));
+        HIPCK(status_clear(status, s));
         GemmProblem g;                       // G = C X^T   (N x m)
         g.M = (int)N; g.N = (int)m; g.K = (int)N;
         g.A = C; g.lda = N; g.B = X; g.ldb = N; g.flags = G_TB;
@@ -1632,10 +1667,11 @@ kf_status mne_solve(int64_t N, int64_t m, int64_t T, const double* X, const doub
         j.B = G; j.ldb = ldm;
         j.C = J; j.ldc = N;
         HIPCK(gemm1(Dt::F64, j, s));
-        HIPCK(hipMemcpyAsync(hstat, status, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(&hstat, status, sizeof hstat, hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
-        if (hstat[0]) {
-            p->err = "mne_solve: X C X^T + R is not positive definite (pivot row " + std::to_string(hstat[3]) + ")";
+        if (hstat.key != kStatusClear) {
+            p->err = "mne_solve: X C X^T + R is not positive definite (pivot row " +
+                     std::to_string(status_row(hstat.key)) + ")";
             return KF_ENOTPD;
         }
         return KF_OK;

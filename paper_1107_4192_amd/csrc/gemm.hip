@@ -564,8 +564,9 @@ __device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int
 }
 
 // V selects a separately named instantiation: 1 for the smoother's N x N x N
-// products of the float64 path, 2 for those of the mixed path, so that profilers
-// report them on their own. MASK is the set of operand
+// products of the float64 path, 2 for those of the mixed path, 3 for the float64
+// products of a smoother pass serialised onto one stream for measurement, so that
+// profilers report them on their own. MASK is the set of operand
 // layouts compiled in (bit L for layout L); each problem of the group picks its own.
 template <typename T, int V, int MASK>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmGroup G) {
@@ -652,7 +653,7 @@ hipError_t launch_fast(const GemmGroup& G, int mask, hipStream_t s) {
 
 }  // namespace
 
-hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s) {
+hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s, hipEvent_t main_done) {
     GemmGroup G;
     int total = 0;
     const int esz = dt == Dt::F64 ? 8 : 4;
@@ -703,12 +704,14 @@ hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s) {
         mask |= 1 << layouts[u];
         if (G.p[u].flags & (G_ALOWER | G_BLOWER | G_BUPPER)) G.remap = 0;
     }
-    const int variant = (G.p[0].flags & G_NXN) ? 1 : (G.p[0].flags & G_NXN_MIXED) ? 2 : 0;
+    const int variant = (G.p[0].flags & G_NXN) ? 1 : (G.p[0].flags & G_NXN_MIXED) ? 2
+                      : (G.p[0].flags & G_NXN_SERIAL) ? 3 : 0;
     hipError_t e;
     if (fast) {
         if (dt == Dt::F64)
             e = variant == 1 ? launch_fast<double, 1>(G, mask, s)
-              : variant == 2 ? launch_fast<double, 2>(G, mask, s) : launch_fast<double, 0>(G, mask, s);
+              : variant == 2 ? launch_fast<double, 2>(G, mask, s)
+              : variant == 3 ? launch_fast<double, 3>(G, mask, s) : launch_fast<double, 0>(G, mask, s);
         else
             e = variant == 2 ? launch_fast<float, 2>(G, mask, s) : launch_fast<float, 0>(G, mask, s);
     } else {
@@ -717,6 +720,7 @@ hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s) {
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
+    if (main_done && (e = hipEventRecord(main_done, s)) != hipSuccess) return e;
     for (int u = 0; u < G.count; ++u) {
         const GemmDesc& p = G.p[u];
         if (p.ksplit <= 1) continue;
@@ -798,15 +802,17 @@ TailSplit choose_tail_split(int tiles, int kiters, int slots, int max_units) {
     return best;
 }
 
-hipError_t gemm_launch_tail(Dt dt, const GemmProblem& p, TailSplit ts, void* ws, hipStream_t s) {
+hipError_t gemm_launch_tail(Dt dt, const GemmProblem& p, TailSplit ts, void* ws, hipStream_t s,
+                            hipEvent_t main_done) {
     GemmProblem g[2] = {p, p};
-    if (ts.k <= 1 || !ws || p.ksplit > 1 || p.tile_off != 0 || p.tile_cnt >= 0) return gemm_launch(dt, g, 1, s);
+    if (ts.k <= 1 || !ws || p.ksplit > 1 || p.tile_off != 0 || p.tile_cnt >= 0)
+        return gemm_launch(dt, g, 1, s, main_done);
     g[0].tile_cnt = ts.full;
     g[1].tile_off = ts.full;
     g[1].ksplit = ts.k;
     g[1].flags |= G_TILEPART;
     g[1].partial = ws;
-    return gemm_launch(dt, g, 2, s);
+    return gemm_launch(dt, g, 2, s, main_done);
 }
 
 }  // namespace kfmeg

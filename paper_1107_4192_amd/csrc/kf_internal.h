@@ -24,6 +24,8 @@ enum GemmFlags : int {
     G_NXN = 512,       // separately named instantiation: smoother N x N x N products, float64 path
     G_NXN_MIXED = 1024,// separately named instantiation: the same products in the mixed-precision path
     G_TILEPART = 2048, // with ksplit > 1: partial sums in one compact slice per tile (tile-wise reduction)
+    G_NXN_SERIAL = 4096,// separately named instantiation: the smoother's float64 products in a pass run on
+                        // one stream (an isolated measurement of the kernel, without concurrent work)
 };
 
 struct GemmProblem {
@@ -49,8 +51,9 @@ constexpr int kMaxProd = 2;    // smoother gain batches in flight at once (side 
 enum class Dt { F64, F32 };
 
 // Enqueue a group of up to kMaxGroup problems sharing one launch (compute type `dt`).
-// Problems with ksplit > 1 are followed by their reduction launch.
-hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s);
+// Problems with ksplit > 1 are followed by their reduction launch. `main_done`, if given, is
+// recorded on s right after the main kernel (before any reduction launch).
+hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s, hipEvent_t main_done = nullptr);
 inline hipError_t gemm1(Dt dt, GemmProblem p, hipStream_t s) { return gemm_launch(dt, &p, 1, s); }
 
 // Tail splitting of one large product: the first `full` tiles (in the problem's tile order)
@@ -65,22 +68,40 @@ int gemm_slots();                          // workgroups resident at once on the
 // Best split for `tiles` equal-cost tiles with `kiters` k-steps each, at most max_units split units.
 TailSplit choose_tail_split(int tiles, int kiters, int slots, int max_units);
 // Launch p with split ts; ws holds (tiles - full) * k tile slices of the compute type.
-hipError_t gemm_launch_tail(Dt dt, const GemmProblem& p, TailSplit ts, void* ws, hipStream_t s);
+hipError_t gemm_launch_tail(Dt dt, const GemmProblem& p, TailSplit ts, void* ws, hipStream_t s,
+                            hipEvent_t main_done = nullptr);
 
 // ---------------------------------------------------------------- Cholesky + inverse
-// Device status word: first failure wins. [0] = failed (1), [1] = which matrix, [2] = step t,
-// [3] = row of the failing pivot.
+// Device status record. `key` holds the failure of smallest (step, row, matrix) seen so far,
+// packed as status_key(); kStatusClear (all ones) means no failure. Failures are merged with a
+// 64-bit atomicMin, so the reported step is the lowest failing one whatever order the batched
+// factorisations finish in. `flag` is set by the non-finite scan of the data.
 enum Which : int { W_S = 1, W_PPRED = 2, W_MNE = 3 };
+struct DevStatus {
+    unsigned long long key;
+    int flag;
+    int pad;
+};
+constexpr unsigned long long kStatusClear = ~0ull;
+__host__ __device__ constexpr unsigned long long status_key(int step, int row, int which) {
+    return ((unsigned long long)(unsigned)step << 32) | ((unsigned long long)(row & 0xFFFFFF) << 8) |
+           (unsigned long long)(which & 0xFF);
+}
+inline int status_step(unsigned long long k) { return (int)(k >> 32); }
+inline int status_row(unsigned long long k) { return (int)((k >> 8) & 0xFFFFFF); }
+inline int status_which(unsigned long long k) { return (int)(k & 0xFF); }
+// Reset a status record on stream s (a kernel, not a memset).
+hipError_t status_clear(DevStatus* st, hipStream_t s);
 
 // Blocked right-looking Cholesky of the SPD matrix held in the lower triangle of W (n x n, ld ldw),
 // fused with the inverse of the factor: on return W's lower triangle holds L (its strict upper
 // triangle is scratch) and Z holds L^{-1} (lower, explicit zeros above the diagonal). Z must not
 // alias W.
-hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, int* status,
+hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, DevStatus* status,
                     int which, int step, hipStream_t s);
 // The same for `count` <= kMaxBatch independent matrices of one size, sharing every launch.
 hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z, int64_t ldz, int count,
-                          int* status, int which, const int* steps, hipStream_t s);
+                          DevStatus* status, int which, const int* steps, hipStream_t s);
 
 // ---------------------------------------------------------------- vector / elementwise kernels
 // e = y - X x  (X: m x N, ld ldx)

@@ -47,6 +47,10 @@ struct Job {
     std::string err;
     int stride = 1;
     size_t reserved = 0;
+    hipEvent_t ready = nullptr;   // recorded on the submitter's stream: inputs are written
+    ~Job() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
 };
 
 constexpr size_t kSlack = (size_t)64 << 10;   // arena alignment of ~60 buffers per plan
@@ -177,6 +181,8 @@ struct kfs_server {
             kf_options o = opt;
             o.checkpoint_stride = stride;
             o.hbm_budget_bytes = j->reserved;
+            // The job's inputs may still be being produced on the submitter's stream.
+            if (j->ready && st) (void)hipStreamWaitEvent(st, j->ready, 0);
             double* xf = static_cast<double*>(arena.alloc((size_t)j->T * j->N * sizeof(double)));
             kf_plan* plan = nullptr;
             kf_status s = xf ? create_plan(&plan, j->N, j->m, j->T, j->X, j->Q, j->R, j->x0, j->P0, &o, st, &arena)
@@ -248,9 +254,16 @@ kf_status kfs_create(kfs_server** out, size_t hbm_budget_bytes, int max_active, 
 
 kf_status kfs_submit(kfs_server* s, int64_t N, int64_t m, int64_t T, const double* X, const double* Q,
                      const double* R, const double* x0, const double* P0, const double* Y, double* x_smooth,
-                     double* Pdiag_smooth, int64_t* job_id) {
+                     double* Pdiag_smooth, void* stream, int64_t* job_id) {
     if (!s || N <= 0 || m <= 0 || T <= 0 || !X || !Q || !R || !x0 || !P0 || !Y || !x_smooth) return KF_EINVAL;
     auto j = std::make_unique<Job>();
+    // Order the job after the work already enqueued on the submitter's stream.
+    if (hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(j->ready, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        if (j->ready) (void)hipEventDestroy(j->ready);
+        (void)hipGetLastError();
+        return KF_EHIP;
+    }
     j->N = N; j->m = m; j->T = T;
     j->X = X; j->Q = Q; j->R = R; j->x0 = x0; j->P0 = P0; j->Y = Y;
     j->xs = x_smooth; j->dPs = Pdiag_smooth;

@@ -197,6 +197,12 @@ __global__ void nonfinite_kernel(const double* v, int64_t n, int* flag) {
     if (badv) atomicOr(flag, 1);
 }
 
+__global__ void status_clear_kernel(DevStatus* st) {
+    st->key = kStatusClear;
+    st->flag = 0;
+    st->pad = 0;
+}
+
 __global__ void diag_kernel(const double* A, int64_t lda, int n, double* out) {
     const int i = blockIdx.x * TPB + threadIdx.x;
     if (i < n) out[i] = A[(int64_t)i * lda + i];
@@ -342,6 +348,11 @@ hipError_t nonfinite_scan(const double* v, int64_t n, int* flag, hipStream_t s) 
     return hipGetLastError();
 }
 
+
+hipError_t status_clear(DevStatus* st, hipStream_t s) {
+    hipLaunchKernelGGL(status_clear_kernel, dim3(1), dim3(1), 0, s, st);
+    return hipGetLastError();
+}
 
 hipError_t diag_copy(const double* A, int64_t lda, int n, double* out, hipStream_t s) {
     hipLaunchKernelGGL(diag_kernel, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, A, lda, n, out);

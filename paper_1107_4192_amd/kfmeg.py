@@ -104,7 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_init_from_mne.restype = ctypes.c_int
     lib.kfs_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(kf_options)]
     lib.kfs_create.restype = ctypes.c_int
-    lib.kfs_submit.argtypes = [vp, i64, i64, i64, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(i64)]
+    lib.kfs_submit.argtypes = [vp, i64, i64, i64, dp, dp, dp, dp, dp, dp, dp, dp, vp, ctypes.POINTER(i64)]
     lib.kfs_submit.restype = ctypes.c_int
     lib.kfs_wait.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
     lib.kfs_wait.restype = ctypes.c_int
@@ -261,9 +261,11 @@ def kf_get_filtered_cov(plan: int, t: int, P_out) -> None:
     _check(lib, st, plan)
 
 
-def kf_set_profiling(plan: int, on: bool) -> None:
+def kf_set_profiling(plan: int, on) -> None:
+    """on: False/0 off, True/1 event-time the smoother's N x N x N products, 2 the same with the
+    smoother serialised onto the plan's stream (each product runs alone)."""
     lib = load_library()
-    _check(lib, lib.kf_set_profiling(plan, int(bool(on))), plan)
+    _check(lib, lib.kf_set_profiling(plan, int(on)), plan)
 
 
 def kf_get_profile(plan: int):
@@ -325,7 +327,9 @@ class Server:
             raise KFError(st, "kfs_create failed")
         self.h = h.value
 
-    def submit(self, X, Q, R, x0, P0, Y, want_diag: bool = True):
+    def submit(self, X, Q, R, x0, P0, Y, want_diag: bool = True, stream=None):
+        """Queue one filter + smoother job. Its work is ordered after everything already enqueued
+        on `stream` (default: the current torch stream), where the inputs may still be produced."""
         m, N = X.shape
         T = Y.shape[0]
         xs = torch.empty((T, N), dtype=torch.float64, device=X.device)
@@ -334,7 +338,7 @@ class Server:
         st = self._lib.kfs_submit(self.h, N, m, T, _dev(X, "X", (m, N)), _dev(Q, "Q", (N, N)),
                                   _dev(R, "R", (m, m)), _dev(x0, "x0", (N,)), _dev(P0, "P0", (N, N)),
                                   _dev(Y, "Y", (T, m)), xs.data_ptr(), ds.data_ptr() if ds is not None else None,
-                                  ctypes.byref(jid))
+                                  _stream_ptr(stream), ctypes.byref(jid))
         if st != KF_OK:
             raise KFError(st, "kfs_submit failed")
         self._keep[jid.value] = (X, Q, R, x0, P0, Y, xs, ds)

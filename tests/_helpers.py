@@ -31,3 +31,15 @@ def eps_P(got, want):
 
 def dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def elem_rel(got, want, floor=1e-3):
+    """Element-wise relative error, max over every element: |g - w| / (|w| + floor * max_i |w_t,i|),
+    with the floor taken per time step (row) so that near-zero entries of a step are compared
+    against that step's scale."""
+    got, want = to_np(got), to_np(want)
+    if got.ndim == 1:
+        got, want = got[None], want[None]
+    scale = np.abs(want).reshape(want.shape[0], -1).max(axis=1)
+    scale = scale.reshape((-1,) + (1,) * (want.ndim - 1))
+    return float((np.abs(got - want) / (np.abs(want) + floor * np.maximum(scale, 1e-300))).max())

@@ -53,3 +53,19 @@ def test_free_orientation_full_size(workload, opt, tol):
     # the smoothed covariance is exactly symmetric
     Ps = res.P_smooth[T - 2]
     assert torch.equal(Ps, Ps.T)
+
+
+def test_free_orientation_checkpointed_full_size(workload):
+    """Checkpoint-and-recompute at N=15372 (the store a budget would not hold): stride 3 over
+    T=3 keeps only P_{3|3}, so the smoother step checked against the oracle reads a recomputed
+    P_{2|2}; mixed precision, float32 store, as in the free-orientation workload."""
+    p, xf, dPf, xs_t, Pcols = workload
+    opt = {"precision": kfmeg.KF_MIXED, "store_fp32": True}
+    full = run(p, **opt)
+    ck = run(p, checkpoint_stride=3, **opt)
+    T = p.T
+    assert torch.equal(ck.x_smooth, full.x_smooth) and torch.equal(ck.Pdiag_smooth, full.Pdiag_smooth)
+    assert torch.equal(ck.P_smooth, full.P_smooth)
+    assert eps_x(ck.x_smooth[T - 2:T - 1], xs_t[None]) <= 1e-4
+    got = to_np(ck.P_smooth[T - 2])[:, COLS]
+    assert np.abs(got - Pcols).max() / np.abs(Pcols).max() <= 1e-4

@@ -137,7 +137,7 @@ def test_deterministic_and_data_independent_covariances():
 
 
 def test_paper_scale_short_horizon():
-    """N=5124, m=306 (the paper's shape) on T=3: every output of the oracle, element by element."""
+    """N=5124, m=306 (the paper's shape) on T=3: every output against the oracle, normwise per step."""
     p = synth.paper(T=3)
     res, _ = gpu_run(p, full=True)
     ref = oracle_run(p)
@@ -183,6 +183,36 @@ def test_non_pd_innovation_reports_step():
         gpu_run(p)
     assert ei.value.status == kfmeg.KF_ENOTPD
     assert "t=1" in str(ei.value)
+
+
+def _null_space_negative_q(seed=21, N=20, m=6, T=12, drop=0.8):
+    """A model whose smoother fails while its filter does not: Q = 0.5 I - drop v v^T with X v = 0.
+    S never sees v, but the v-eigenvalue of P_{t|t} falls by drop - 0.5 = 0.3 per step from 1, so
+    P_{t+1|t} = P_{t|t} + Q is not positive definite from t = 3 on (eqn11)."""
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(m, N))
+    v = np.linalg.svd(X)[2][-1]                       # X v = 0 up to rounding
+    Q = 0.5 * np.eye(N) - drop * np.outer(v, v)
+    Q = (Q + Q.T) / 2.0
+    return synth.Problem("nullq", X, Q, 0.3 * np.eye(m), np.zeros(N), np.eye(N), rng.normal(size=(T, m)))
+
+
+@pytest.mark.parametrize("opt", [{}, {"checkpoint_stride": 4}, {"precision": kfmeg.KF_MIXED, "store_fp32": True}])
+def test_non_pd_smoother_gain_reports_lowest_step(opt):
+    p = _null_space_negative_q()
+    with pytest.raises(np.linalg.LinAlgError):        # the oracle fails on the same model
+        xf, Pf, _ = oracle.kf_filter(p.X, p.Q, p.R, p.x0, p.P0, p.Y)
+        oracle.rts_smooth(xf, Pf, p.Q)
+    ks = kfmeg.KalmanSmoother(dev(p.X), dev(p.Q), dev(p.R), dev(p.x0), dev(p.P0), T_max=p.T, **opt)
+    try:
+        res = ks.filter(dev(p.Y))                     # the filter itself succeeds
+        with pytest.raises(kfmeg.KFError) as ei:
+            ks.smooth(res)
+    finally:
+        ks.close()
+    assert ei.value.status == kfmeg.KF_ENOTPD
+    # steps 3 .. T-1 all fail, across two gain batches formed in parallel: the lowest is reported
+    assert "P_{t+1|t}" in str(ei.value) and "t=3 " in str(ei.value), str(ei.value)
 
 
 def test_smooth_before_filter_is_state_error():

@@ -121,3 +121,24 @@ def test_cancel_queued_job():
         assert torch.equal(outs[1][0], xa)
     finally:
         srv.close()
+
+
+def test_inputs_written_asynchronously_on_the_submitters_stream():
+    """Inputs produced by GPU work still in flight on the caller's stream: the job must wait for it."""
+    p = make_jobs([(300, 60, 8)], seed0=300)[0]
+    xa, da = alone(p)
+    srv = kfmeg.Server(max_active=2)
+    side = torch.cuda.Stream()
+    try:
+        with torch.cuda.stream(side):
+            busy = torch.ones((4096, 4096), dtype=torch.float64, device="cuda")
+            for _ in range(20):                      # keep the stream busy before Y is written
+                busy = busy @ busy * (1.0 / 4096)
+            Y = torch.zeros((p.T, p.m), dtype=torch.float64, device="cuda")
+            Y.copy_(torch.as_tensor(p.Y), non_blocking=False)
+            Y.mul_(1.0)
+            jid = srv.submit(dev(p.X), dev(p.Q), dev(p.R), dev(p.x0), dev(p.P0), Y, stream=side)
+        xs, ds, _ = srv.wait(jid)
+    finally:
+        srv.close()
+    assert torch.equal(xs, xa) and torch.equal(ds, da)

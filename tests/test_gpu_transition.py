@@ -1,8 +1,9 @@
 """Sparse transition F (eqn3; the six-neighbour model of eqn2) through the C ABI.
 
 Filter, smoother and mean-only smoother with F against the oracle run with the same
-dense F: 1e-10 normwise on the float64 path, 1e-4 mixed; checkpoint-recompute equal
-to the full store bit for bit; F = I given explicitly equal to the random walk.
+dense F: 1e-10 normwise on the float64 path, 1e-4 mixed (eqn13 stays float64 under F);
+checkpoint-recompute equal to the full store bit for bit; F = I given explicitly equal to
+the random walk.
 """
 import numpy as np
 import pytest
@@ -55,16 +56,14 @@ def test_neighbourhood_tiny_precisions_checkpointing_batch_and_means():
     assert eps_d(full.Pdiag_smooth, dPs) <= 1e-10
     ck, _ = gpu_run(p, checkpoint_stride=4)
     assert torch.equal(ck.x_smooth, full.x_smooth) and torch.equal(ck.Pdiag_smooth, full.Pdiag_smooth)
-    # Mixed precision: the eqn13 products run in float32. This F (half of it a neighbour
-    # average) leaves P_{t+1|t} about 1e3 times worse conditioned than the random walk does
-    # (cond ~1.7e5 against ~1.6e2 at t = 5), and the smoothed variances, some 20 times smaller,
-    # come out at a normwise error of about 3e-4 -- the means stay at 2e-7. The bound for
-    # diag P_{t|T} is therefore 1e-3 here, against 1e-4 for the random walk.
+    # Mixed precision: with F the gain A_t has a large norm (P_{t+1|t} about 1e3 times worse
+    # conditioned than under the random walk), so the library keeps eqn13 in float64 there; the
+    # float32 downdate and store remain. Held to the mixed-precision bound of 1e-4.
     for store32 in (False, True):
         mixed, _ = gpu_run(p, precision=kfmeg.KF_MIXED, store_fp32=store32)
         e = (eps_x(mixed.x_smooth, xs), eps_d(mixed.Pdiag_smooth, dPs), eps_d(mixed.Pdiag_filt, dPf))
         print("neighbourhood mixed errors (x_smooth, diag P_smooth, diag P_filt), float32 store:", store32, e)
-        assert e[0] <= 1e-4 and e[1] <= 1e-3 and e[2] <= 1e-4
+        assert max(e) <= 1e-4, e
     # batched data sets and the mean-only smoother under the same F
     rng = np.random.default_rng(9)
     Ys = np.stack([p.Y, p.Y + np.std(p.Y) * rng.normal(size=p.Y.shape)])
@@ -92,14 +91,20 @@ def test_identity_transition_is_random_walk():
     assert eps_d(eye.Pdiag_smooth, to_np(walk.Pdiag_smooth)) <= 1e-13
 
 
-def test_neighbourhood_paper_scale_short_horizon():
-    p = synth.neighbourhood(T=3)
-    res, _ = gpu_run(p)
-    xf, Pf, dPf, xs, Ps, dPs = oracle_run(p)
-    errs = {"x_filt": eps_x(res.x_filt, xf), "x_smooth": eps_x(res.x_smooth, xs),
-            "d_smooth": eps_d(res.Pdiag_smooth, dPs)}
-    print("paper-scale neighbourhood errors", errs)
-    assert max(errs.values()) <= 1e-10, errs
+@pytest.fixture(scope="module")
+def neighbourhood_paper():
+    p = synth.neighbourhood(T=4)
+    return p, oracle_run(p)
+
+
+@pytest.mark.parametrize("opt,tol", [({}, 1e-10), ({"precision": kfmeg.KF_MIXED, "store_fp32": True}, 1e-4)])
+def test_neighbourhood_paper_scale_short_horizon(neighbourhood_paper, opt, tol):
+    p, (xf, Pf, dPf, xs, Ps, dPs) = neighbourhood_paper
+    res, _ = gpu_run(p, **opt)
+    errs = {"x_filt": eps_x(res.x_filt, xf), "d_filt": eps_d(res.Pdiag_filt, dPf),
+            "x_smooth": eps_x(res.x_smooth, xs), "d_smooth": eps_d(res.Pdiag_smooth, dPs)}
+    print("paper-scale neighbourhood errors", opt, errs)
+    assert max(errs.values()) <= tol, errs
 
 
 def test_malformed_transition_rejected():
