@@ -203,6 +203,27 @@ kf_status mne_solve(int64_t N, int64_t m, int64_t T, const double* X, const doub
                     const double* R, const double* Y, double* J, void* stream);
 
 /*
+ * mne_solve_noalloc: mne_solve for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, launches and results (bit for bit) as mne_solve,
+ * but its workspace comes from one fixed 64 MiB device array of the library
+ * (one per GPU, held until the process ends) instead of an allocation: it calls
+ * no hipMalloc, hipFree or other allocating routine. The workspace of a call is
+ * 8 (N ldm + 2 m ldm + 2 m ldT + k m^2) bytes plus a 16-byte status record, each
+ * part rounded up to 256 bytes, with ldm = m and ldT = T rounded up to
+ * multiples of 16 and k = min(32, max(1, N / 128)); a shape that needs more than
+ * 64 MiB returns KF_EINVAL before any launch (N = 5124, m = 306 fits up to
+ * T of about 5800). The array keeps the last call's contents; everything a call
+ * reads from it is written first by that call. Calls on one GPU share the array:
+ * calls that overlap in time on the same GPU (on different streams or threads)
+ * race and must be serialised by the caller. Synchronises `stream` before it
+ * returns; KF_ENOTPD if X C X^T + R is not positive definite, KF_EHIP if the
+ * array's device address cannot be obtained.
+ */
+kf_status mne_solve_noalloc(int64_t N, int64_t m, int64_t T, const double* X, const double* C,
+                            const double* R, const double* Y, double* J, void* stream);
+
+/*
  * kf_init_from_mne: the parameter set-up of Section 2.4. Computes the MNE
  * estimates J_t (eqn5, prior covariance C) for every row of Y (T x m, T >= 3),
  * returns x0_out = J_1 (the estimate of the first sample) and

@@ -1602,84 +1602,13 @@ void kf_destroy(kf_plan* p) {
 
 const char* kf_last_error(const kf_plan* p) { return p ? p->err.c_str() : g_err.c_str(); }
 
-kf_status mne_solve(int64_t N, int64_t m, int64_t T, const double* X, const double* C, const double* R,
-                    const double* Y, double* J, void* stream) {
-    g_err.clear();
-    if (N <= 0 || m <= 0 || T <= 0 || !X || !C || !R || !Y || !J) {
-        g_err = "mne_solve: sizes must be positive and pointers non-null";
-        return KF_EINVAL;
-    }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    kf_plan tmp;   // only for the error string and allocation bookkeeping
-    kf_plan* p = &tmp;
-    const int64_t ldm = round_up(m, 16), ldT = round_up(T, 16);
-    double *G, *S, *Lis, *U, *V, *part;
-    DevStatus* status;
-    DevStatus hstat{};
-    kf_status st = KF_OK;
-    auto cleanup = [&](kf_status r) {
-        for (void* a : tmp.allocs) (void)hipFree(a);
-        tmp.allocs.clear();
-        if (r != KF_OK && g_err.empty()) g_err = tmp.err;
-        return r;
-    };
-#define MALLOC(ptr, n)                                       \
-    if ((st = alloc(p, &(ptr), (n))) != KF_OK) return cleanup(st);
-    MALLOC(G, (size_t)N * ldm);
-    MALLOC(S, (size_t)m * ldm);
-    MALLOC(Lis, (size_t)m * ldm);
-    MALLOC(U, (size_t)m * ldT);
-    MALLOC(V, (size_t)m * ldT);
-    MALLOC(part, (size_t)32 * m * m);
-    MALLOC(status, 1);
-#undef MALLOC
-    auto run = [&]() -> kf_status {
-        HIPCK(status_clear(status, s));
-        GemmProblem g;                       // G = C X^T   (N x m)
-        g.M = (int)N; g.N = (int)m; g.K = (int)N;
-        g.A = C; g.lda = N; g.B = X; g.ldb = N; g.flags = G_TB;
-        g.C = G; g.ldc = ldm;
-        HIPCK(gemm1(Dt::F64, g, s));
-        GemmProblem h;                       // S = X G + R
-        h.M = (int)m; h.N = (int)m; h.K = (int)N;
-        h.A = X; h.lda = N; h.B = G; h.ldb = ldm;
-        h.Cin = R; h.ldcin = m; h.beta = 1.0;
-        h.C = S; h.ldc = ldm;
-        h.ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(32, N / 128));
-        h.partial = part;
-        HIPCK(gemm1(Dt::F64, h, s));
-        HIPCK(chol_inv(S, ldm, Lis, ldm, (int)m, status, W_MNE, 0, s));
-        GemmProblem u;                       // U = Li Y^T   (m x T)
-        u.M = (int)m; u.N = (int)T; u.K = (int)m;
-        u.A = Lis; u.lda = ldm; u.flags = G_ALOWER | G_TB;
-        u.B = Y; u.ldb = m;
-        u.C = U; u.ldc = ldT;
-        HIPCK(gemm1(Dt::F64, u, s));
-        GemmProblem v;                       // V = Li^T U = S^{-1} Y^T
-        v.M = (int)m; v.N = (int)T; v.K = (int)m;
-        v.A = Lis; v.lda = ldm; v.flags = G_TA;
-        v.B = U; v.ldb = ldT;
-        v.C = V; v.ldc = ldT;
-        HIPCK(gemm1(Dt::F64, v, s));
-        GemmProblem j;                       // J = V^T G^T   (T x N)
-        j.M = (int)T; j.N = (int)N; j.K = (int)m;
-        j.A = V; j.lda = ldT; j.flags = G_TA | G_TB;
-        j.B = G; j.ldb = ldm;
-        j.C = J; j.ldc = N;
-        HIPCK(gemm1(Dt::F64, j, s));
-        HIPCK(hipMemcpyAsync(&hstat, status, sizeof hstat, hipMemcpyDeviceToHost, s));
-        HIPCK(hipStreamSynchronize(s));
-        if (hstat.key != kStatusClear) {
-            p->err = "mne_solve: X C X^T + R is not positive definite (pivot row " +
-                     std::to_string(status_row(hstat.key)) + ")";
-            return KF_ENOTPD;
-        }
-        return KF_OK;
-    };
-    st = run();
-    if (st != KF_OK) g_err = tmp.err;
-    return cleanup(st);
-}
+}  // extern "C"
+
+namespace kfmeg {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace kfmeg
+
+extern "C" {
 
 kf_status kf_init_from_mne(int64_t N, int64_t m, int64_t T, const double* X, const double* C, const double* R,
                            const double* Y, double reg, double* x0_out, double* Q_out, void* stream) {

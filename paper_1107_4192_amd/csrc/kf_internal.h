@@ -149,6 +149,9 @@ hipError_t nonfinite_scan(const double* v, int64_t n, int* flag, hipStream_t s);
 // store diag of a square double matrix to out
 hipError_t diag_copy(const double* A, int64_t lda, int n, double* out, hipStream_t s);
 
+// Message returned by kf_last_error(NULL) for the calling thread (calls without a plan).
+void set_last_error(const std::string& msg);
+
 // ---------------------------------------------------------------- sparse transition (eqn3)
 struct Csr {
     int n = 0;                    // square n x n

@@ -26,7 +26,7 @@ EXPORTS = ("kf_default_options", "kf_create", "kf_filter", "kf_smooth", "kf_get_
            "kfs_create", "kfs_submit", "kfs_wait", "kfs_job_info", "kfs_get_stats", "kfs_last_error",
            "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch", "kfd_gemm_tail", "kf_smooth_means",
            "kf_smooth_means_batch", "kfs_cancel",
-           "kf_set_transition", "kf_smooth_assoc")
+           "kf_set_transition", "kf_smooth_assoc", "mne_solve_noalloc")
 
 
 class KFError(RuntimeError):
@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_get_filtered_cov.restype = ctypes.c_int
     lib.mne_solve.argtypes = [i64, i64, i64, dp, dp, dp, dp, dp, vp]
     lib.mne_solve.restype = ctypes.c_int
+    lib.mne_solve_noalloc.argtypes = [i64, i64, i64, dp, dp, dp, dp, dp, vp]
+    lib.mne_solve_noalloc.restype = ctypes.c_int
     lib.kf_destroy.argtypes = [vp]
     lib.kf_destroy.restype = None
     lib.kf_last_error.argtypes = [vp]
@@ -291,6 +293,19 @@ def mne_solve(X, C, R, Y, J=None, stream=None):
         J = torch.empty((T, N), dtype=torch.float64, device=X.device)
     st = lib.mne_solve(N, m, T, _dev(X, "X", (m, N)), _dev(C, "C", (N, N)), _dev(R, "R", (m, m)),
                        _dev(Y, "Y", (T, m)), _dev(J, "J", (T, N)), _stream_ptr(stream))
+    _check(lib, st, None)
+    return J
+
+
+def mne_solve_noalloc(X, C, R, Y, J, stream=None):
+    """mne_solve without device allocation: the workspace is the library's fixed 64 MiB array.
+    J (T x N) must be given; calls that overlap on one GPU race (see kfmeg.h)."""
+    lib = load_library()
+    _need_gpu()
+    m, N = X.shape
+    T = Y.shape[0]
+    st = lib.mne_solve_noalloc(N, m, T, _dev(X, "X", (m, N)), _dev(C, "C", (N, N)), _dev(R, "R", (m, m)),
+                               _dev(Y, "Y", (T, m)), _dev(J, "J", (T, N)), _stream_ptr(stream))
     _check(lib, st, None)
     return J
 
