@@ -53,6 +53,19 @@ int kfd_gemm_tail(int dtype, int M, int N, int K, int flags, const void* A, int6
  */
 int kfd_chol_inv(int n, double* W, int64_t ldw, double* Z, int64_t ldz, int* pivot_row, void* stream);
 
+/*
+ * X = A^{-1} B for the SPD matrix A in the lower triangle of W (n x n, ld ldw)
+ * and B (n x n, ld ldb), the way the smoother forms its gain (eqn11): an
+ * outer-blocked Cholesky A = L L^T with diagonal blocks of width nb (the last
+ * one ragged; only the diagonal blocks are inverted), then the blocked solves
+ * Y = L^{-1} B and X = L^{-T} Y. On return W's lower triangle holds L (the
+ * strict upper triangle is scratch); X (n x n, ld ldx) must not overlap W or B.
+ * Returns 0, 2 with *pivot_row set if a pivot is not positive (or not finite),
+ * 1 on bad arguments, 4 on a HIP error (workspace is allocated per call).
+ */
+int kfd_spd_solve(int n, int nb, double* W, int64_t ldw, const double* B, int64_t ldb, double* X, int64_t ldx,
+                  int* pivot_row, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,8 @@
 // latency of the sequential sweep is shared by every matrix of the batch.
 #include "kf_internal.h"
 
+#include <algorithm>
+
 namespace kfmeg {
 
 namespace {
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(NTD) void potrf_inv_diag(DiagBatch B, int64_t ldw, 
 }  // namespace
 
 hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z, int64_t ldz, int count,
-                          DevStatus* status, int which, const int* steps, hipStream_t s) {
+                          DevStatus* status, int which, const int* steps, hipStream_t s, int row_base) {
     if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
     hipError_t e;
     for (int b = 0; b < count; ++b)
@@ -132,7 +134,8 @@ hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z
                 db.Z[b] = z(b, k0, k0);
                 db.step[b] = steps ? steps[b] : 0;
             }
-            hipLaunchKernelGGL(potrf_inv_diag, dim3(count), dim3(NTD), 0, s, db, ldw, ldz, kb, status, which, k0);
+            hipLaunchKernelGGL(potrf_inv_diag, dim3(count), dim3(NTD), 0, s, db, ldw, ldz, kb, status, which,
+                               row_base + k0);
             if ((e = hipGetLastError()) != hipSuccess) return e;
 
             GemmProblem pr[kMaxGroup];
@@ -207,7 +210,164 @@ hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z
 
 hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, DevStatus* status, int which,
                     int step, hipStream_t s) {
-    return chol_inv_batch(n, &W, ldw, &Z, ldz, 1, status, which, &step, s);
+    return chol_inv_batch(n, &W, ldw, &Z, ldz, 1, status, which, &step, s, 0);
+}
+
+// ------------------------------------------------------------------ outer-blocked factorisation and solves
+// For the smoother gain (eqn11) the inverse of the whole factor is not needed: with L from an
+// outer-blocked Cholesky of P_{t+1|t} (diagonal blocks of width nb factored and inverted by
+// chol_inv_batch above), A_t^T = L^{-T} (L^{-1} F P_{t|t}) is two blocked triangular solves whose
+// off-diagonal work is products with K up to n, and whose diagonal blocks are applied as products
+// with the small inverses Li_kk. Every launch covers the whole batch.
+
+namespace {
+
+// The gain's products run as their own named kernel instantiation (profiling).
+hipError_t gain_launch(GemmProblem* pr, int count, hipStream_t s) {
+    for (int u = 0; u < count; ++u) pr[u].flags |= G_GAIN;
+    return gemm_launch(Dt::F64, pr, count, s);
+}
+
+// Outer blocks of width nb; a remainder narrower than nb / 4 joins the last full block (so the
+// last block is up to gain_block_width(n, nb) wide) rather than costing a sweep of its own.
+struct Blocks {
+    int n, nb;
+    int count() const {
+        const int full = n / nb, rem = n - full * nb;
+        if (full == 0) return 1;
+        return (rem == 0 || rem < nb / 4) ? full : full + 1;
+    }
+    int lo(int k) const { return k * nb; }
+    int hi(int k) const { return k == count() - 1 ? n : (k + 1) * nb; }
+};
+
+}  // namespace
+
+int gain_block_width(int n, int nb) {
+    const Blocks bl{n, nb};
+    return bl.hi(bl.count() - 1) - bl.lo(bl.count() - 1) > nb ? bl.hi(bl.count() - 1) - bl.lo(bl.count() - 1)
+                                                               : std::min(n, nb);
+}
+
+hipError_t chol_blocked_batch(int n, int nb, double* const* W, int64_t ldw, double* const* D, int64_t ldd,
+                              double* const* Tb, int64_t ldt, int count, DevStatus* status, int which,
+                              const int* steps, hipStream_t s) {
+    if (count < 1 || count > kMaxBatch || nb < 1 || ldd < gain_block_width(n, nb) || ldt < n)
+        return hipErrorInvalidValue;
+    const Blocks bl{n, nb};
+    hipError_t e;
+    for (int k = 0; k < bl.count(); ++k) {
+        const int r0 = bl.lo(k), r1 = bl.hi(k), nbk = r1 - r0, nr = n - r1;
+        double* Wd[kMaxBatch];
+        double* Dd[kMaxBatch];
+        for (int b = 0; b < count; ++b) {
+            Wd[b] = W[b] + (int64_t)r0 * ldw + r0;
+            Dd[b] = D[b] + (int64_t)r0 * ldd;
+        }
+        // L_kk and Li_kk of the diagonal block (its trailing part already updated)
+        if ((e = chol_inv_batch(nbk, Wd, ldw, Dd, ldd, count, status, which, steps, s, r0)) != hipSuccess) return e;
+        if (nr == 0) break;
+        GemmProblem pr[kMaxGroup];
+        for (int b = 0; b < count; ++b) {     // panel, transposed: Tb = Li_kk A_{>k,k}^T = L_{>k,k}^T
+            GemmProblem& g = pr[b];
+            g.M = nbk; g.N = nr; g.K = nbk;
+            g.A = Dd[b]; g.lda = ldd; g.flags = G_ALOWER | G_TB;
+            g.B = W[b] + (int64_t)r1 * ldw + r0; g.ldb = ldw;
+            g.C = Tb[b]; g.ldc = ldt;
+        }
+        if ((e = gain_launch(pr, count, s)) != hipSuccess) return e;
+        for (int b = 0; b < count; ++b) {     // trailing: A_{>k,>k} -= L_{>k,k} L_{>k,k}^T  (lower tiles)
+            GemmProblem& g = pr[b];
+            g = GemmProblem();
+            g.M = nr; g.N = nr; g.K = nbk;
+            g.A = Tb[b]; g.lda = ldt; g.flags = G_TA | G_LOWER;
+            g.B = Tb[b]; g.ldb = ldt;
+            g.alpha = -1.0; g.beta = 1.0;
+            g.Cin = W[b] + (int64_t)r1 * ldw + r1; g.ldcin = ldw;
+            g.C = W[b] + (int64_t)r1 * ldw + r1; g.ldc = ldw;
+        }
+        if ((e = gain_launch(pr, count, s)) != hipSuccess) return e;
+        TransposeBatch tb;                    // the panel into place: W[r1 + i][r0 + c] = Tb[c][i]
+        for (int b = 0; b < count; ++b) {
+            tb.src[b] = Tb[b];
+            tb.dst[b] = W[b] + (int64_t)r1 * ldw + r0;
+            tb.dst32[b] = nullptr;
+        }
+        if ((e = transpose_batch(tb, count, nbk, nr, ldt, ldw, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t trsm_lower_batch(int n, int nb, const double* const* W, int64_t ldw, const double* const* D, int64_t ldd,
+                            double* const* Tb, int64_t ldt, const double* const* B, int64_t ldb, double* const* Y,
+                            int64_t ldy, int count, hipStream_t s) {
+    if (count < 1 || count > kMaxBatch || ldt < n) return hipErrorInvalidValue;
+    const Blocks bl{n, nb};
+    hipError_t e;
+    GemmProblem pr[kMaxGroup];
+    for (int k = 0; k < bl.count(); ++k) {
+        const int r0 = bl.lo(k), nbk = bl.hi(k) - r0;
+        if (k > 0) {                          // Tb = B_k - L_{k,<k} Y_{<k}
+            for (int b = 0; b < count; ++b) {
+                GemmProblem& g = pr[b];
+                g = GemmProblem();
+                g.M = nbk; g.N = n; g.K = r0;
+                g.A = W[b] + (int64_t)r0 * ldw; g.lda = ldw;
+                g.B = Y[b]; g.ldb = ldy;
+                g.alpha = -1.0; g.beta = 1.0;
+                g.Cin = B[b] + (int64_t)r0 * ldb; g.ldcin = ldb;
+                g.C = Tb[b]; g.ldc = ldt;
+            }
+            if ((e = gain_launch(pr, count, s)) != hipSuccess) return e;
+        }
+        for (int b = 0; b < count; ++b) {     // Y_k = Li_kk (B_k - ...)
+            GemmProblem& g = pr[b];
+            g = GemmProblem();
+            g.M = nbk; g.N = n; g.K = nbk;
+            g.A = D[b] + (int64_t)r0 * ldd; g.lda = ldd; g.flags = G_ALOWER;
+            if (k > 0) { g.B = Tb[b]; g.ldb = ldt; }
+            else { g.B = B[b]; g.ldb = ldb; }
+            g.C = Y[b] + (int64_t)r0 * ldy; g.ldc = ldy;
+        }
+        if ((e = gain_launch(pr, count, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t trsm_upper_t_batch(int n, int nb, const double* const* W, int64_t ldw, const double* const* D,
+                              int64_t ldd, double* const* Tb, int64_t ldt, const double* const* Y, int64_t ldy,
+                              double* const* Z, int64_t ldz, int count, hipStream_t s) {
+    if (count < 1 || count > kMaxBatch || ldt < n) return hipErrorInvalidValue;
+    const Blocks bl{n, nb};
+    hipError_t e;
+    GemmProblem pr[kMaxGroup];
+    for (int k = bl.count() - 1; k >= 0; --k) {
+        const int r0 = bl.lo(k), r1 = bl.hi(k), nbk = r1 - r0;
+        if (r1 < n) {                         // Tb = Y_k - L_{>k,k}^T Z_{>k}
+            for (int b = 0; b < count; ++b) {
+                GemmProblem& g = pr[b];
+                g = GemmProblem();
+                g.M = nbk; g.N = n; g.K = n - r1;
+                g.A = W[b] + (int64_t)r1 * ldw + r0; g.lda = ldw; g.flags = G_TA;
+                g.B = Z[b] + (int64_t)r1 * ldz; g.ldb = ldz;
+                g.alpha = -1.0; g.beta = 1.0;
+                g.Cin = Y[b] + (int64_t)r0 * ldy; g.ldcin = ldy;
+                g.C = Tb[b]; g.ldc = ldt;
+            }
+            if ((e = gain_launch(pr, count, s)) != hipSuccess) return e;
+        }
+        for (int b = 0; b < count; ++b) {     // Z_k = Li_kk^T (Y_k - ...)
+            GemmProblem& g = pr[b];
+            g = GemmProblem();
+            g.M = nbk; g.N = n; g.K = nbk;
+            g.A = D[b] + (int64_t)r0 * ldd; g.lda = ldd; g.flags = G_TA | G_AUPPER;
+            if (r1 < n) { g.B = Tb[b]; g.ldb = ldt; }
+            else { g.B = Y[b] + (int64_t)r0 * ldy; g.ldb = ldy; }
+            g.C = Z[b] + (int64_t)r0 * ldz; g.ldc = ldz;
+        }
+        if ((e = gain_launch(pr, count, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace kfmeg

@@ -13,9 +13,10 @@
 // since K = P_pred X^T S^{-1} = C^T Li and K X P_pred = C^T C.
 //
 // Smoother step t (eqn11-eqn13, RTS reading), P_t = P_{t|t}, Pn = P_{t+1|t}:
-//   L Li = chol(Pn)                      N x N   blocked Cholesky fused with L^{-1}, eight steps
-//                                                per batch, batches formed on side streams
-//   H   = (P_t F^T) Li^T ;  A_t = H Li   N x N   two triangular MFMA products: A_t = P_t F^T Pn^{-1}
+//   L = chol(Pn)                         N x N   outer-blocked Cholesky (diagonal blocks inverted),
+//                                                eight steps per batch, batches on side streams
+//   Y = L^{-1} F P_t ; A_t^T = L^{-T} Y  N x N   two blocked triangular solves, then A_t^T is
+//                                                transposed in place: A_t = P_t F^T Pn^{-1}
 //   x_{t|T} = x_{t|t} + A_t (x_{t+1|T} - F x_{t|t})
 //   D   = P_{t+1|T} - Pn ;  M = A_t D    N x N   elementwise pass, MFMA GEMM (last wave split along K)
 //   P_{t|T} = P_t + M A_t^T              N x N   lower tiles + mirror, diagonal out
@@ -69,7 +70,11 @@ struct kf_plan {
     // gains, and the upcast P_{t|t} they came from, rotate through nprod + 1 sets.
     int gbatch = 1;
     int nprod = 1;                          // gain batches in flight at once, one side stream each
-    double *W[kMaxProd][kMaxBatch] = {}, *Li[kMaxProd][kMaxBatch] = {};   // factorisation scratch per stream
+    // per side stream and batch slot: W (P_{t+1|t}, then its factor L), Li (L^{-1} F P_{t|t}) and Dg
+    // (inverses of L's diagonal blocks, gnb columns wide, then an gnb x N solve panel)
+    double *W[kMaxProd][kMaxBatch] = {}, *Li[kMaxProd][kMaxBatch] = {}, *Dg[kMaxProd][kMaxBatch] = {};
+    int gnb = kGainBlock;                   // outer block of the gain's factorisation and solves
+    int64_t gld = 0;                        // leading dimension of the diagonal-block inverses
     double* Ab[kMaxProd + 1][kMaxBatch] = {};   // gain sets: nprod + 1 in rotation
     double* Pt64[kMaxProd + 1][kMaxBatch] = {};
     float* A32[kMaxProd + 1][kMaxBatch] = {};
@@ -230,11 +235,19 @@ size_t bck_bytes(int64_t N, int64_t m, int64_t T, int stride) {
     return stride > 1 ? 8 * (size_t)(T / stride + 1) * (size_t)m * round_up(N, 16) : 0;
 }
 
-// np: gain batches in flight (np scratch sets W, Li and np + 1 gain sets).
+// Outer block width of the gain's factorisation for order N, and the leading dimension of the
+// stacked diagonal-block inverses (the widest block, rounded up).
+int gain_block(int64_t N) { return (int)std::min<int64_t>(kGainBlock, N); }
+int64_t gain_ld(int64_t N) { return round_up(gain_block_width((int)N, gain_block(N)), 16); }
+// Elements of one Dg buffer: N x gld inverses, then a (widest block) x ldN solve panel.
+size_t gain_scratch_elems(int64_t N) { return (size_t)gain_ld(N) * (size_t)(N + round_up(N, 16)); }
+
+// np: gain batches in flight (np scratch sets W, Li, Dg and np + 1 gain sets).
 size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int gb, int np = 1) {
     const int64_t ldN = round_up(N, 16), ldm = round_up(m, 16);
     const size_t NN = (size_t)N * ldN;
     size_t b = 0;
+    b += 8 * (size_t)np * gb * gain_scratch_elems(N);
     b += 8 * (2 * NN + 2 * (size_t)m * ldN + (size_t)m * ldm + 2 * (size_t)N);   // Q, P0, X, XQ, R, x0
     b += 8 * (2 * (size_t)m * ldN + 3 * (size_t)m * ldm + 3 * (size_t)N + 64);
     b += 8 * (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);                 // split-K partials
@@ -653,8 +666,12 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     p->partial_elems = (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);
     ALLOC(p->partial, p->partial_elems);
     ALLOC(p->dstatus, 1);
+    p->gnb = gain_block(N);
+    p->gld = gain_ld(N);
     for (int b = 0; b < p->gbatch; ++b) {
-        for (int q = 0; q < p->nprod; ++q) { ALLOC(p->W[q][b], NN); ALLOC(p->Li[q][b], NN); }
+        for (int q = 0; q < p->nprod; ++q) {
+            ALLOC(p->W[q][b], NN); ALLOC(p->Li[q][b], NN); ALLOC(p->Dg[q][b], gain_scratch_elems(N));
+        }
         for (int set = 0; set <= p->nprod; ++set) {
             ALLOC(p->Ab[set][b], NN);
             if (p->store32) ALLOC(p->Pt64[set][b], NN);
@@ -874,16 +891,22 @@ kf_status recompute_segment(kf_plan* p, int64_t t0, int64_t t1, int64_t T) {
 }
 
 // Smoother gains for a batch of steps (eqn11): A_t = P_{t|t} F^T P_{t+1|t}^{-1} for each
-// t = ts[b], formed as H = P_t F^T Li^T, A_t = H Li with L Li = chol(P_{t+1|t}), into gain
-// set `set` (H stays in the stream's W buffers). The steps are independent given the stored
-// P_{t|t}, so every launch covers the whole batch.
+// t = ts[b], into gain set `set`. With L the Cholesky factor of P_{t+1|t} (outer-blocked; only
+// its diagonal blocks are inverted),
+//     Y = L^{-1} F P_{t|t},   A_t^T = L^{-T} Y,
+// two blocked triangular solves; A_t^T is then transposed in place (and rounded to float32 for
+// the mixed path). Y = H^T with H = P_{t|t} F^T L^{-T} stays in the stream's Li buffers (the
+// associative smoother uses H H^T). The steps are independent given the stored P_{t|t}, so
+// every launch covers the whole batch.
 kf_status gain_batch(kf_plan* p, int set, int q, int count, const int64_t* ts, const void* const* Pt,
                      const bool* is32, hipStream_t s) {
     double* const* Wq = p->W[q];
-    double* const* Liq = p->Li[q];
+    double* const* Yq = p->Li[q];
     const int N = (int)p->N;
     const int64_t ld = p->ldN;
     const double* P64[kMaxBatch];
+    const double* rhs[kMaxBatch];
+    double *Db[kMaxBatch], *Tb[kMaxBatch];
     int steps[kMaxBatch];
     for (int b = 0; b < count; ++b) {
         P64[b] = static_cast<const double*>(Pt[b]);
@@ -892,34 +915,31 @@ kf_status gain_batch(kf_plan* p, int set, int q, int count, const int64_t* ts, c
             P64[b] = p->Pt64[set][b];
         }
         if (p->hasF) {
-            // G_t = P_t F^T (kept in A_t's buffer until A_t overwrites it); W = F G_t + Q (eqn7)
-            HIPCK(dense_sparse_t(p->F, P64[b], ld, p->Ab[set][b], ld, s));
-            HIPCK(spmm_rows(p->F, p->Ab[set][b], ld, 1.0, p->Q, ld, 1.0, nullptr, 0, 0.0, Wq[b], false, ld, s));
+            // G_t = P_t F^T (in Y's buffer until the solves need it); W = F G_t + Q (eqn7);
+            // right-hand side F P_t in A_t's buffer (read by the first solve only)
+            HIPCK(dense_sparse_t(p->F, P64[b], ld, Yq[b], ld, s));
+            HIPCK(spmm_rows(p->F, Yq[b], ld, 1.0, p->Q, ld, 1.0, nullptr, 0, 0.0, Wq[b], false, ld, s));
+            HIPCK(spmm_rows(p->F, P64[b], ld, 1.0, nullptr, 0, 0.0, nullptr, 0, 0.0, p->Ab[set][b], false, ld, s));
+            rhs[b] = p->Ab[set][b];
         } else {
             // W = P_t + Q  (= P_{t+1|t}, eqn7)
             HIPCK(axpby3(N, N, Wq[b], false, ld, P64[b], false, ld, p->Q, false, ld, 1.0, nullptr, false, 0, 0.0,
                          s));
+            rhs[b] = P64[b];
         }
+        Db[b] = p->Dg[q][b];
+        Tb[b] = p->Dg[q][b] + (size_t)N * p->gld;
         steps[b] = (int)ts[b] + 1;
     }
-    HIPCK(chol_inv_batch(N, Wq, ld, Liq, ld, count, p->dstatus, W_PPRED, steps, s));
-    // A_t = P_t Li^T Li. H = P_t Li^T goes into W (L is not needed any more). The first product
-    // takes Li as a transposed operand (upper triangular in (k, l)), the second as stored (lower
-    // triangular in (k, j)); each skips the zero triangle of its K range.
-    GemmProblem g[kMaxBatch], h[kMaxBatch];
+    HIPCK(chol_blocked_batch(N, p->gnb, Wq, ld, Db, p->gld, Tb, ld, count, p->dstatus, W_PPRED, steps, s));
+    HIPCK(trsm_lower_batch(N, p->gnb, Wq, ld, Db, p->gld, Tb, ld, rhs, ld, Yq, ld, count, s));
+    HIPCK(trsm_upper_t_batch(N, p->gnb, Wq, ld, Db, p->gld, Tb, ld, Yq, ld, p->Ab[set], ld, count, s));
+    TransposeInPlace tr;
     for (int b = 0; b < count; ++b) {
-        g[b].M = N; g[b].N = N; g[b].K = N;    // H = P_t F^T Li^T   (B(l,k) = Li[k][l], zero for l > k)
-        g[b].A = p->hasF ? p->Ab[set][b] : P64[b]; g[b].lda = ld;
-        g[b].B = Liq[b]; g[b].ldb = ld; g[b].flags = G_TB | G_BUPPER;
-        g[b].C = Wq[b]; g[b].ldc = ld;
-        h[b].M = N; h[b].N = N; h[b].K = N;    // A_t = H Li     (B(k,j) = Li[k][j], zero for k < j)
-        h[b].A = Wq[b]; h[b].lda = ld;
-        h[b].B = Liq[b]; h[b].ldb = ld; h[b].flags = G_BLOWER;
-        h[b].C = p->Ab[set][b]; h[b].ldc = ld;
-        if (mixed(p)) { h[b].C32 = p->A32[set][b]; h[b].ldc32 = ld; }
+        tr.A[b] = p->Ab[set][b];
+        tr.A32[b] = mixed(p) ? p->A32[set][b] : nullptr;
     }
-    TRY(big_group(p, Dt::F64, g, count, (double)count * N * N * N, s));
-    TRY(big_group(p, Dt::F64, h, count, (double)count * N * N * N, s));
+    HIPCK(transpose_square_inplace(tr, count, N, ld, s));
     return KF_OK;
 }
 
@@ -1189,7 +1209,8 @@ kf_status smooth_means_impl(kf_plan* p, int64_t B, double* xs) {
 // Time-parallel smoother: eqn12 and eqn13 regrouped as a suffix scan with an associative
 // operator. Each step t < T-1 contributes the element
 //     E_t = A_t,   g_t = x_{t|t} - A_t F x_{t|t},   L_t = P_{t|t} - H_t H_t^T
-// with H_t = P_{t|t} F^T Li_t^T the first factor of the gain (A_t = H_t Li_t), so that
+// with H_t = P_{t|t} F^T C_t^{-T} the first factor of the gain, C_t the Cholesky factor of
+// P_{t+1|t} (A_t = H_t C_t^{-1}), so that
 // H_t H_t^T = A_t F P_{t|t} = A_t P_{t+1|t} A_t^T; step T-1 contributes (0, x_{T|T}, P_{T|T}).
 // With
 //     (E, g, L) o (E', g', L') = (E E', E g' + g, E L' E^T + L)
@@ -1266,10 +1287,10 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
                 Fx = u;
             }
             HIPCK(gemv_smooth(E[t], ld, xf + t * N, Fx, zero, xs + t * N, n, s));    // g_t = x - A F x
-            // L_t = P_t - H_t H_t^T (lower tiles + mirror) over the slot; H_t is still in W
+            // L_t = P_t - H_t H_t^T (lower tiles + mirror) over the slot; H_t^T is still in Li
             g[b].M = n; g[b].N = n; g[b].K = n;
-            g[b].A = p->W[0][b]; g[b].lda = ld; g[b].B = p->W[0][b]; g[b].ldb = ld;
-            g[b].flags = G_TB | G_LOWER | G_MIRROR;
+            g[b].A = p->Li[0][b]; g[b].lda = ld; g[b].B = p->Li[0][b]; g[b].ldb = ld;
+            g[b].flags = G_TA | G_LOWER | G_MIRROR;
             g[b].alpha = -1.0; g[b].beta = 1.0; g[b].Cin = L[t]; g[b].ldcin = ld;
             g[b].C = L[t]; g[b].ldc = ld;
         }

@@ -189,6 +189,8 @@ __device__ __forceinline__ void decode_tile(const GemmDesc& P, int local, int& b
     if (P.flags & G_LOWER) tri_decode(local, bm, bn);
     else if (P.flags & G_ALOWER) {            // longest tiles (largest K range) first
         bm = P.tiles_m() - 1 - local / P.tiles_n(); bn = local % P.tiles_n();
+    } else if (P.flags & G_AUPPER) {
+        bm = local / P.tiles_n(); bn = local % P.tiles_n();
     } else if (P.flags & G_BLOWER) {
         bn = local / P.tiles_m(); bm = local % P.tiles_m();
     } else if (P.flags & G_BUPPER) {
@@ -327,6 +329,7 @@ __global__ __launch_bounds__(NT) void gemm_generic_kernel(GemmGroup G) {
     if (P.flags & G_ALOWER) khi = min(khi, i0 + BM);
     if (P.flags & G_BUPPER) khi = min(khi, j0 + BN);
     if (P.flags & G_BLOWER) klo = max(klo, j0);
+    if (P.flags & G_AUPPER) klo = max(klo, i0);
     if (P.ksplit > 1) {
         const int span = max(khi - klo, 0);
         const int chunk = ((span + P.ksplit - 1) / P.ksplit + BK - 1) / BK * BK;
@@ -505,6 +508,7 @@ __device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int
     if (P.flags & G_ALOWER) khi = min(khi, i0 + BM);
     if (P.flags & G_BUPPER) khi = min(khi, j0 + BN);
     if (P.flags & G_BLOWER) klo = max(klo, j0);
+    if (P.flags & G_AUPPER) klo = max(klo, i0);
     if (P.ksplit > 1) {
         const int span = max(khi - klo, 0);
         const int chunk = ((span + P.ksplit - 1) / P.ksplit + BK - 1) / BK * BK;
@@ -565,8 +569,9 @@ __device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int
 
 // V selects a separately named instantiation: 1 for the smoother's N x N x N
 // products of the float64 path, 2 for those of the mixed path, 3 for the float64
-// products of a smoother pass serialised onto one stream for measurement, so that
-// profilers report them on their own. MASK is the set of operand
+// products of a smoother pass serialised onto one stream for measurement, 4 for the
+// smoother gain's blocked Cholesky and triangular solves, so that profilers report
+// them on their own. MASK is the set of operand
 // layouts compiled in (bit L for layout L); each problem of the group picks its own.
 template <typename T, int V, int MASK>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmGroup G) {
@@ -702,16 +707,17 @@ hipError_t gemm_launch(Dt dt, GemmProblem* probs, int count, hipStream_t s, hipE
     G.remap = 1;
     for (int u = 0; u < G.count; ++u) {
         mask |= 1 << layouts[u];
-        if (G.p[u].flags & (G_ALOWER | G_BLOWER | G_BUPPER)) G.remap = 0;
+        if (G.p[u].flags & (G_ALOWER | G_AUPPER | G_BLOWER | G_BUPPER)) G.remap = 0;
     }
     const int variant = (G.p[0].flags & G_NXN) ? 1 : (G.p[0].flags & G_NXN_MIXED) ? 2
-                      : (G.p[0].flags & G_NXN_SERIAL) ? 3 : 0;
+                      : (G.p[0].flags & G_NXN_SERIAL) ? 3 : (G.p[0].flags & G_GAIN) ? 4 : 0;
     hipError_t e;
     if (fast) {
         if (dt == Dt::F64)
             e = variant == 1 ? launch_fast<double, 1>(G, mask, s)
               : variant == 2 ? launch_fast<double, 2>(G, mask, s)
-              : variant == 3 ? launch_fast<double, 3>(G, mask, s) : launch_fast<double, 0>(G, mask, s);
+              : variant == 3 ? launch_fast<double, 3>(G, mask, s)
+              : variant == 4 ? launch_fast<double, 4>(G, mask, s) : launch_fast<double, 0>(G, mask, s);
         else
             e = variant == 2 ? launch_fast<float, 2>(G, mask, s) : launch_fast<float, 0>(G, mask, s);
     } else {

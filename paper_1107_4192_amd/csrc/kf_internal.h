@@ -26,6 +26,8 @@ enum GemmFlags : int {
     G_TILEPART = 2048, // with ksplit > 1: partial sums in one compact slice per tile (tile-wise reduction)
     G_NXN_SERIAL = 4096,// separately named instantiation: the smoother's float64 products in a pass run on
                         // one stream (an isolated measurement of the kernel, without concurrent work)
+    G_AUPPER = 8192,   // A(i,k) = 0 for k < i (stored zeros): K range starts at the tile's first row
+    G_GAIN = 16384,    // separately named instantiation: the smoother gain's blocked Cholesky and solves
 };
 
 struct GemmProblem {
@@ -47,6 +49,7 @@ struct GemmProblem {
 constexpr int kMaxGroup = 16;
 constexpr int kMaxBatch = 8;   // matrices per batched factorisation (two problems each per group)
 constexpr int kMaxProd = 2;    // smoother gain batches in flight at once (side streams)
+constexpr int kGainBlock = 1024;  // outer block of the smoother gain's Cholesky and triangular solves
 
 enum class Dt { F64, F32 };
 
@@ -100,8 +103,33 @@ hipError_t status_clear(DevStatus* st, hipStream_t s);
 hipError_t chol_inv(double* W, int64_t ldw, double* Z, int64_t ldz, int n, DevStatus* status,
                     int which, int step, hipStream_t s);
 // The same for `count` <= kMaxBatch independent matrices of one size, sharing every launch.
+// `row_base` is added to the pivot row reported in the status record.
 hipError_t chol_inv_batch(int n, double* const* W, int64_t ldw, double* const* Z, int64_t ldz, int count,
-                          DevStatus* status, int which, const int* steps, hipStream_t s);
+                          DevStatus* status, int which, const int* steps, hipStream_t s, int row_base = 0);
+
+// Widest outer block of the blocked factorisation below for order n and block nb: nb, except that
+// a remainder narrower than nb / 4 joins the last block (and n itself when n <= nb).
+int gain_block_width(int n, int nb);
+// Outer-blocked Cholesky of `count` SPD matrices held in the lower triangles of W (n x n, ld ldw):
+// diagonal blocks of width nb (the last one ragged) are factored and inverted by chol_inv_batch,
+// each panel is formed transposed in Tb, L_{>k,k}^T = Li_kk A_{>k,k}^T, and the trailing matrix
+// is updated with K = nb. On return W's lower triangle holds L (its strict upper triangle is
+// scratch) and D (n x nb, ld ldd >= nb) holds the inverse of diagonal block k in rows
+// [k nb, k nb + nb_k), lower triangular with explicit zeros (ldd >= gain_block_width(n, nb)).
+// Tb: gain_block_width(n, nb) x n scratch, ld ldt >= n.
+hipError_t chol_blocked_batch(int n, int nb, double* const* W, int64_t ldw, double* const* D, int64_t ldd,
+                              double* const* Tb, int64_t ldt, int count, DevStatus* status, int which,
+                              const int* steps, hipStream_t s);
+// Y = L^{-1} B (B, Y: n x n) with L, D from chol_blocked_batch; block row k is
+// Y_k = Li_kk (B_k - L_{k,<k} Y_{<k}). Y must not alias B, W or D; Tb is scratch.
+hipError_t trsm_lower_batch(int n, int nb, const double* const* W, int64_t ldw, const double* const* D, int64_t ldd,
+                            double* const* Tb, int64_t ldt, const double* const* B, int64_t ldb, double* const* Y,
+                            int64_t ldy, int count, hipStream_t s);
+// Z = L^{-T} Y (n x n); block row k is Z_k = Li_kk^T (Y_k - L_{>k,k}^T Z_{>k}), last block first.
+// Z must not alias Y, W or D; Tb is scratch.
+hipError_t trsm_upper_t_batch(int n, int nb, const double* const* W, int64_t ldw, const double* const* D,
+                              int64_t ldd, double* const* Tb, int64_t ldt, const double* const* Y, int64_t ldy,
+                              double* const* Z, int64_t ldz, int count, hipStream_t s);
 
 // ---------------------------------------------------------------- vector / elementwise kernels
 // e = y - X x  (X: m x N, ld ldx)
@@ -142,6 +170,21 @@ hipError_t copy2d_r32(int rows, int cols, double* dst, int64_t ldd, const void* 
 hipError_t diff_center(const double* J, int64_t ldj, int T, int N, double* Dc, int64_t ldd, hipStream_t s);
 // A[i][i] += v
 hipError_t add_diag(double* A, int64_t lda, int n, double v, hipStream_t s);
+// dst_q = src_q^T for q < count: src rows x cols (ld lds), dst cols x rows (ld ldd); with dst32_q
+// also a float32 copy of dst_q (same ld). Out of place: dst must not overlap src.
+struct TransposeBatch {
+    const double* src[kMaxBatch];
+    double* dst[kMaxBatch];
+    float* dst32[kMaxBatch];
+};
+hipError_t transpose_batch(const TransposeBatch& T, int count, int rows, int cols, int64_t lds, int64_t ldd,
+                           hipStream_t s);
+// A_q = A_q^T in place for square n x n matrices (ld lda); with A32_q also a float32 copy.
+struct TransposeInPlace {
+    double* A[kMaxBatch];
+    float* A32[kMaxBatch];
+};
+hipError_t transpose_square_inplace(const TransposeInPlace& T, int count, int n, int64_t lda, hipStream_t s);
 // set a rows x cols block to zero
 hipError_t zero2d(int rows, int cols, double* dst, int64_t ldd, hipStream_t s);
 // scan n values for NaN / Inf; sets *flag = 1 if any

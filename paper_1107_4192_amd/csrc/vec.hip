@@ -197,6 +197,70 @@ __global__ void nonfinite_kernel(const double* v, int64_t n, int* flag) {
     if (badv) atomicOr(flag, 1);
 }
 
+// dst = src^T through a 32 x 33 LDS tile (both sides coalesced); blockIdx.z picks the matrix.
+constexpr int TT = 32, TR = 8;
+__global__ __launch_bounds__(TT * TR) void transpose_kernel(TransposeBatch T, int rows, int cols, int64_t lds,
+                                                            int64_t ldd) {
+    __shared__ double tile[TT][TT + 1];
+    const double* src = T.src[blockIdx.z];
+    double* dst = T.dst[blockIdx.z];
+    float* dst32 = T.dst32[blockIdx.z];
+    const int c0 = blockIdx.x * TT, r0 = blockIdx.y * TT;
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
+#pragma unroll
+    for (int k = 0; k < TT; k += TR) {
+        const int r = r0 + ty + k, c = c0 + tx;
+        if (r < rows && c < cols) tile[ty + k][tx] = src[(int64_t)r * lds + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TT; k += TR) {
+        const int c = c0 + ty + k, r = r0 + tx;       // dst[c][r] = src[r][c]
+        if (r < rows && c < cols) {
+            const double v = tile[tx][ty + k];
+            dst[(int64_t)c * ldd + r] = v;
+            if (dst32) dst32[(int64_t)c * ldd + r] = (float)v;
+        }
+    }
+}
+
+// In-place transpose of square matrices: block (pair t, matrix z) swaps tiles (I, J) and (J, I),
+// I <= J, through LDS; every element belongs to exactly one pair, so blocks never overlap.
+__global__ __launch_bounds__(TT * TR) void transpose_square_kernel(TransposeInPlace T, int n, int64_t lda) {
+    __shared__ double ta[TT][TT + 1], tb[TT][TT + 1];
+    double* A = T.A[blockIdx.y];
+    float* A32 = T.A32[blockIdx.y];
+    // pair index -> (J >= I) on the lower triangle of tile indices
+    const int t = blockIdx.x;
+    int J = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((J + 1) * (J + 2) / 2 <= t) ++J;
+    while (J * (J + 1) / 2 > t) --J;
+    const int I = t - J * (J + 1) / 2;
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
+    const int i0 = I * TT, j0 = J * TT;
+#pragma unroll
+    for (int k = 0; k < TT; k += TR) {
+        const int r = ty + k;
+        if (i0 + r < n && j0 + tx < n) ta[r][tx] = A[(int64_t)(i0 + r) * lda + j0 + tx];   // tile (I, J)
+        if (j0 + r < n && i0 + tx < n) tb[r][tx] = A[(int64_t)(j0 + r) * lda + i0 + tx];   // tile (J, I)
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TT; k += TR) {
+        const int r = ty + k;
+        if (i0 + r < n && j0 + tx < n) {          // (I, J) <- (J, I)^T
+            const double v = tb[tx][r];
+            A[(int64_t)(i0 + r) * lda + j0 + tx] = v;
+            if (A32) A32[(int64_t)(i0 + r) * lda + j0 + tx] = (float)v;
+        }
+        if (I != J && j0 + r < n && i0 + tx < n) {   // (J, I) <- (I, J)^T
+            const double v = ta[tx][r];
+            A[(int64_t)(j0 + r) * lda + i0 + tx] = v;
+            if (A32) A32[(int64_t)(j0 + r) * lda + i0 + tx] = (float)v;
+        }
+    }
+}
+
 __global__ void status_clear_kernel(DevStatus* st) {
     st->key = kStatusClear;
     st->flag = 0;
@@ -348,6 +412,23 @@ hipError_t nonfinite_scan(const double* v, int64_t n, int* flag, hipStream_t s) 
     return hipGetLastError();
 }
 
+
+hipError_t transpose_batch(const TransposeBatch& T, int count, int rows, int cols, int64_t lds, int64_t ldd,
+                           hipStream_t s) {
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const dim3 grid((cols + TT - 1) / TT, (rows + TT - 1) / TT, count);
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(TT * TR), 0, s, T, rows, cols, lds, ldd);
+    return hipGetLastError();
+}
+
+hipError_t transpose_square_inplace(const TransposeInPlace& T, int count, int n, int64_t lda, hipStream_t s) {
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    if (n <= 0) return hipSuccess;
+    const int nt = (n + TT - 1) / TT;
+    hipLaunchKernelGGL(transpose_square_kernel, dim3(nt * (nt + 1) / 2, count), dim3(TT * TR), 0, s, T, n, lda);
+    return hipGetLastError();
+}
 
 hipError_t status_clear(DevStatus* st, hipStream_t s) {
     hipLaunchKernelGGL(status_clear_kernel, dim3(1), dim3(1), 0, s, st);

@@ -26,7 +26,7 @@ EXPORTS = ("kf_default_options", "kf_create", "kf_filter", "kf_smooth", "kf_get_
            "kfs_create", "kfs_submit", "kfs_wait", "kfs_job_info", "kfs_get_stats", "kfs_last_error",
            "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch", "kfd_gemm_tail", "kf_smooth_means",
            "kf_smooth_means_batch", "kfs_cancel",
-           "kf_set_transition", "kf_smooth_assoc", "mne_solve_noalloc")
+           "kf_set_transition", "kf_smooth_assoc", "mne_solve_noalloc", "kfd_spd_solve")
 
 
 class KFError(RuntimeError):
@@ -130,6 +130,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kfd_gemm_tail.restype = ctypes.c_int
     lib.kfd_chol_inv.argtypes = [ctypes.c_int, dp, i64, dp, i64, ctypes.POINTER(ctypes.c_int), vp]
     lib.kfd_chol_inv.restype = ctypes.c_int
+    lib.kfd_spd_solve.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64, dp, i64, dp, i64, ctypes.POINTER(ctypes.c_int),
+                                  vp]
+    lib.kfd_spd_solve.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -402,6 +405,7 @@ class Server:
 
 # ---------------------------------------------------------------- kernel-level hooks (tests)
 G_TA, G_TB, G_LOWER, G_MIRROR, G_ALOWER, G_BLOWER, G_BUPPER = 1, 2, 4, 8, 16, 32, 64
+G_AUPPER = 8192
 
 
 def kfd_gemm(A, B, M, N, K, flags=0, alpha=1.0, beta=0.0, Cin=None, C=None, ksplit=1, stream=None):
@@ -444,6 +448,21 @@ def kfd_chol_inv(W, Z=None, stream=None):
     if st != 0:
         raise KFError(st, f"kfd_chol_inv failed (pivot row {piv.value})")
     return Z
+
+
+def kfd_spd_solve(W, B, nb: int, X=None, stream=None):
+    """X = A^-1 B with A in the lower triangle of W (overwritten by its factor L) by the smoother gain's
+    outer-blocked Cholesky (block width nb) and blocked solves. Raises KFError(KF_ENOTPD) with the pivot row."""
+    lib = load_library()
+    n = W.shape[0]
+    if X is None:
+        X = torch.empty((n, n), dtype=torch.float64, device=W.device)
+    piv = ctypes.c_int(-1)
+    st = lib.kfd_spd_solve(n, nb, W.data_ptr(), W.stride(0), B.data_ptr(), B.stride(0), X.data_ptr(), X.stride(0),
+                           ctypes.byref(piv), _stream_ptr(stream))
+    if st != 0:
+        raise KFError(st, f"kfd_spd_solve failed (pivot row {piv.value})")
+    return X
 
 
 @dataclass

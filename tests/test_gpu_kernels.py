@@ -2,8 +2,9 @@
 
 Each is compared with a plain float64 CPU computation of the same operation:
 the MFMA GEMM (every layout, triangular and split-K mode, float64 and float32
-operands, ragged sizes spanning several 128-tiles) and the blocked Cholesky
-fused with the inverse of its factor.
+operands, ragged sizes spanning several 128-tiles), the blocked Cholesky
+fused with the inverse of its factor, and the outer-blocked Cholesky with
+blocked triangular solves that forms the smoother gain.
 """
 import numpy as np
 import pytest
@@ -166,5 +167,47 @@ def test_chol_inv_reports_first_bad_pivot(n, row):
     W = torch.tensor(A, device="cuda")
     with pytest.raises(kfmeg.KFError) as ei:
         F.kfd_chol_inv(W)
+    assert ei.value.status == kfmeg.KF_ENOTPD
+    assert f"pivot row {row}" in str(ei.value)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n,k", [(200, 200), (300, 130), (129, 257)])
+def test_gemm_a_upper_transposed(dtype, n, k):
+    # U^T X with U lower triangular: A(i,k) = U[k][i], zero for k < i (upper in (i,k))
+    g = torch.Generator().manual_seed(3 * n + k)
+    U = torch.tril(torch.randn(n, n, generator=g, dtype=torch.float64)).to(dtype)
+    X = torch.randn(n, k, generator=g, dtype=torch.float64).to(dtype)
+    C = F.kfd_gemm(_padded(U), _padded(X), n, k, n, F.G_TA | F.G_AUPPER).cpu()
+    ref = U.double().T @ X.double()
+    tol = 1e-12 if dtype == torch.float64 else 2e-5
+    assert (C - ref).abs().max() <= tol * ref.abs().max()
+
+
+@pytest.mark.parametrize("n,nb", [(1, 1024), (63, 1024), (300, 128), (300, 64), (1000, 256), (1025, 1024),
+                                  (2100, 1024), (2100, 512)])
+def test_blocked_spd_solve(n, nb):
+    """The smoother gain's factorisation and solves: several outer blocks with a ragged last one."""
+    A = _spd(n, 7 * n + nb, cond=1e3)
+    rng = np.random.default_rng(n)
+    B = rng.normal(size=(n, n))
+    W = torch.tril(torch.tensor(A, device="cuda")) + torch.triu(torch.full((n, n), 7.0, device="cuda",
+                                                                            dtype=torch.float64), 1)
+    X = F.kfd_spd_solve(W, torch.tensor(B, device="cuda"), nb).cpu().numpy()
+    L = np.tril(W.cpu().numpy())
+    Lref = np.linalg.cholesky(A)
+    assert np.abs(L - Lref).max() <= 1e-12 * np.abs(Lref).max() * max(1, n) ** 0.5
+    ref = np.linalg.solve(A, B)
+    assert np.abs(X - ref).max() <= 1e-9 * np.abs(ref).max()      # cond 1e3
+    assert np.abs(A @ X - B).max() <= 1e-11 * np.abs(B).max() * max(1, n) ** 0.5
+
+
+@pytest.mark.parametrize("n,nb,row", [(300, 128, 200), (300, 128, 5), (2100, 1024, 2050)])
+def test_blocked_spd_solve_reports_bad_pivot(n, nb, row):
+    A = _spd(n, 3, cond=10)
+    A[row, row] = -1.0
+    W = torch.tensor(A, device="cuda")
+    with pytest.raises(kfmeg.KFError) as ei:
+        F.kfd_spd_solve(W, torch.eye(n, dtype=torch.float64, device="cuda"), nb)
     assert ei.value.status == kfmeg.KF_ENOTPD
     assert f"pivot row {row}" in str(ei.value)
