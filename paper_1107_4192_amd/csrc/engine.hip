@@ -30,6 +30,8 @@
 #include "arena.h"
 #include "../../include/kfmeg.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -125,6 +127,19 @@ struct kf_plan {
 namespace {
 
 thread_local std::string g_err;
+
+// roctx range around the host-side enqueue of one step or batch (visible in a marker trace;
+// a no-op without a profiler).
+struct Range {
+    Range(const char* fmt, long long a, long long b = -1) {
+        char buf[96];
+        snprintf(buf, sizeof buf, fmt, a, b);
+        roctxRangePushA(buf);
+    }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -812,6 +827,7 @@ static kf_status filter_impl(kf_plan* p, int64_t B, int64_t T, const double* Y, 
     const bool direct = !p->store32 && p->stride == 1;   // store slot t is the working P
     const double* prev64 = p->P0;
     for (int64_t t = 0; t < T; ++t) {
+        Range r("kf_filter step t=%lld", (long long)t + 1);
         double* out64 = direct ? static_cast<double*>(slot_ptr(p, t)) : p->Pw[t & 1];
         float* out32 = nullptr;
         if (!slot64(p) && kept(p, t, T)) out32 = static_cast<float*>(slot_ptr(p, slot_of(p, t, T)));
@@ -1029,6 +1045,7 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
     auto run_chain = [&](int set, int count, const int64_t* ts, const void* const* Pt) -> kf_status {
         for (int b = 0; b < count; ++b) {
             const int64_t u = ts[b];
+            Range r("kf_smooth step t=%lld", (long long)u + 1);
             double* Ps_out = p->Ps[u & 1];
             TRY(chain_step(p, set, b, u, Pt[b], p->Ps[(u + 1) & 1], Ps_out, xf, xs, Pdiag ? Pdiag + u * N : nullptr));
             if (Pfull)
@@ -1064,6 +1081,8 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
         const int np = p->nprod, ns = p->nprod + 1;
         auto produce = [&](size_t k) -> kf_status {
             const int q = (int)(k % np), set = (int)(k % ns);
+            Range r("kf_smooth gain batch t=%lld..%lld", (long long)batches[k].ts[batches[k].count - 1] + 1,
+                    (long long)batches[k].ts[0] + 1);
             if (k >= (size_t)ns) HIPCK(hipStreamWaitEvent(p->s2[q], p->ev_chain[set], 0));   // chain k - ns done
             TRY(gain_batch(p, set, q, batches[k].count, batches[k].ts, batches[k].Pt, batches[k].is32, p->s2[q]));
             HIPCK(hipEventRecord(p->ev_gain[set], p->s2[q]));
@@ -1092,6 +1111,7 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
                 // segment of non-kept steps containing t: (previous checkpoint, t]
                 seg_lo = (t + 1) / p->stride * p->stride;
                 seg_hi = t;
+                Range r("kf_smooth recompute t=%lld..%lld", (long long)seg_lo + 1, (long long)seg_hi + 1);
                 TRY(recompute_segment(p, seg_lo, seg_hi, T));
             }
             int64_t ts[kMaxBatch];
@@ -1104,7 +1124,10 @@ kf_status smooth_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull) {
                 is32[count] = kept(p, t - count, T) ? !slot64(p) : s32;   // checkpoints float64, segment as stored
                 ++count;
             }
-            TRY(gain_batch(p, 0, 0, count, ts, Pt, is32, s));
+            {
+                Range r("kf_smooth gain batch t=%lld..%lld", (long long)ts[count - 1] + 1, (long long)ts[0] + 1);
+                TRY(gain_batch(p, 0, 0, count, ts, Pt, is32, s));
+            }
             TRY(run_chain(0, count, ts, Pt));
             t -= count;
         }

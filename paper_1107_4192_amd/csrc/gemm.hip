@@ -559,6 +559,10 @@ __device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int
 #pragma unroll
                     for (int b = 0; b < 4; ++b) acc[a][b] = Acc<T>::mfma(fa[a], fb[b], acc[a][b]);
             }
+            // Every MFMA of this k-tile is issued before the next tile is stored: the stores wait
+            // for the prefetch loads, and kept after the MFMAs those loads get the whole k-tile's
+            // MFMA time to arrive (the compiler otherwise hoists the stores above a third of them).
+            __builtin_amdgcn_sched_barrier(0);
             stash<T>(As + (cur ^ 1) * (BK * BM), ra, !TA, tid);
             stash<T>(Bs + (cur ^ 1) * (BK * BN), rb, TB, tid);
             __syncthreads();
