@@ -44,8 +44,9 @@ struct DiagBatch {
 // Thread t owns column c = t % 64 at rows g, g+4, ..., g+60 (g = t / 64) of both the
 // matrix being factored (a) and U, the inverse of its factor with the row scaling
 // deferred (L^{-1}[i][c] = U[i][c] / L[i][i], U starts as the identity). Step j
-// publishes column j below the pivot d_j (colbuf, zero at and above it) and row j
-// of U through LDS, double buffered so that one barrier per step suffices; then
+// publishes column j from the pivot d_j down (colbuf, zero above it) and row j of U
+// through LDS, double buffered so that one barrier per step suffices; then, with
+// colbuf read as zero at and above the pivot,
 //     a[i] -= colbuf[i] colbuf[c] / d_j   (c > j: the Schur complement)
 //     u[i] -= colbuf[i] U[j][c] / d_j     (c <= j: forward substitution)
 // one FMA each. Column j of L (colbuf / sqrt(d_j)) is collected in LDS and written
@@ -55,7 +56,6 @@ __global__ __launch_bounds__(NTD) void potrf_inv_diag(DiagBatch B, int64_t ldw, 
                                                       DevStatus* status, int which, int row0) {
     __shared__ double colbuf[2][NB];
     __shared__ double urow[2][NB];
-    __shared__ double piv[2];
     __shared__ double invs[NB];
     __shared__ double Ls[NB][NB + 1];
     double* W = B.W[blockIdx.x];
@@ -73,32 +73,39 @@ __global__ __launch_bounds__(NTD) void potrf_inv_diag(DiagBatch B, int64_t ldw, 
 #pragma unroll 1
     for (int j = 0; j < NB; ++j) {
         const int buf = j & 1, rj = j >> 2;
+        // column j from the diagonal down (the pivot included), and row j of U
         if (c == j) {
 #pragma unroll
-            for (int r = 0; r < NB / 4; ++r) colbuf[buf][g + 4 * r] = (g + 4 * r > j) ? a[r] : 0.0;
-            if (g == (j & 3)) piv[buf] = a[rj];
+            for (int r = 0; r < NB / 4; ++r) colbuf[buf][g + 4 * r] = (g + 4 * r >= j) ? a[r] : 0.0;
         }
         if (g == (j & 3)) urow[buf][c] = u[rj];
         __syncthreads();
-        const double d = piv[buf];
-        if (!(d > 0.0) || !isfinite(d)) {       // same value in every thread: uniform exit
-            bad = j;
-            break;
-        }
+        // every LDS read of the step is issued at once, ahead of the pivot's arithmetic
+        const double d = colbuf[buf][j];
+        const double cbc = colbuf[buf][c];
+        const double urc = urow[buf][c];
+        double cb[NB / 4];
+#pragma unroll
+        for (int r = 0; r < NB / 4; ++r) cb[r] = colbuf[buf][g + 4 * r];
+        const bool ok = d > 0.0 && isfinite(d);  // the same in every thread: a uniform exit below
         double y = __builtin_amdgcn_rsq(d);
         y = y * (1.5 - 0.5 * d * y * y);
         y = y * (1.5 - 0.5 * d * y * y);
         const double inv2 = y * y;
-        const double ma = c > j ? colbuf[buf][c] * inv2 : 0.0;
-        const double mu = c <= j ? urow[buf][c] * inv2 : 0.0;
+        const double ma = c > j ? cbc * inv2 : 0.0;
+        const double mu = c <= j ? urc * inv2 : 0.0;
 #pragma unroll
         for (int r = 0; r < NB / 4; ++r) {
-            const double cb = colbuf[buf][g + 4 * r];
-            a[r] = fma(-cb, ma, a[r]);
-            u[r] = fma(-cb, mu, u[r]);
+            const double v = (g + 4 * r > j) ? cb[r] : 0.0;     // rows below the pivot only
+            a[r] = fma(-v, ma, a[r]);
+            u[r] = fma(-v, mu, u[r]);
         }
-        if (g == 0) Ls[c][j] = c > j ? colbuf[buf][c] * y : (c == j ? d * y : 0.0);
+        if (g == 0) Ls[c][j] = c > j ? cbc * y : (c == j ? d * y : 0.0);
         if (tid == 0) invs[j] = y;
+        if (!ok) {                               // checked after the step so that its reads issue together
+            bad = j;
+            break;
+        }
     }
     __syncthreads();
 #pragma unroll

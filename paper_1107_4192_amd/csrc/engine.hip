@@ -52,10 +52,19 @@ struct kf_plan {
     double *X = nullptr, *Q = nullptr, *R = nullptr, *x0 = nullptr, *P0 = nullptr;
     double* XQ = nullptr;                   // X Q (m x N): X (P + Q) = X P + X Q
     // filter workspace
-    double *Bm = nullptr, *Cm = nullptr, *S = nullptr, *Lis = nullptr, *e = nullptr, *w = nullptr, *xw = nullptr;
-    double* Gmm = nullptr;                  // X C_{t-1}^T (m x m) for the recursive update of B
+    double *Bm = nullptr, *e = nullptr, *w = nullptr, *xw = nullptr;
+    // Innovation covariance without the noise, St = X P_{t|t-1} X^T (m x m), kept from step to step,
+    // Sw = St + R its factorisation workspace, XQX = X Q X^T, Hm = L_t^{-1} R; the inverse factor
+    // L_t^{-1} of the last two steps (step t in slot t & 1)
+    double *St = nullptr, *Sw = nullptr, *XQX = nullptr, *Hm = nullptr;
+    double* Li2[2] = {nullptr, nullptr};
+    double* Gm = nullptr;                   // G_t = X C_t^T (m x m) for the recursion of B
+    double* Sck = nullptr;                  // checkpointed store: St at every segment start
+    // C_t = L_t^{-1} B_t of the last two steps (step t in slot t & 1): the downdate of step t may
+    // still be reading C_t while step t + 1 forms C_{t+1}
+    double* Cm2[2] = {nullptr, nullptr};
+    float* Cm32x[2] = {nullptr, nullptr};
     double* Bck = nullptr;                  // checkpointed store: B_t at every segment start (t % stride == 0)
-    float* Cm32 = nullptr;
     double* partial = nullptr;
     size_t partial_elems = 0;
     double* Pw[2] = {nullptr, nullptr};     // float64 working pair (store in float32 or checkpointed)
@@ -90,6 +99,9 @@ struct kf_plan {
     void* tail_ws64 = nullptr;              // mixed plan with a transition F: eqn13 runs in float64
     hipStream_t s2[kMaxProd] = {};
     hipEvent_t ev_start = nullptr, ev_gain[kMaxProd + 1] = {}, ev_chain[kMaxProd + 1] = {};
+    // filter: L_t^{-1} formed, G_t formed, B_t refreshed (t % kBRefresh == 0), N-side of step t done,
+    // C_t formed, downdate t done; slot t & 1
+    hipEvent_t ev_fl[2] = {}, ev_fg[2] = {}, ev_fr[2] = {}, ev_fa[2] = {}, ev_cc[2] = {}, ev_dd[2] = {};
     // status
     DevStatus* dstatus = nullptr;
     DevStatus* hstatus = nullptr;
@@ -245,9 +257,9 @@ size_t factor_bytes(int64_t N, int64_t m, int64_t T) {
     return 8 * (size_t)T * ((size_t)m * ldN + (size_t)m * ldm + (size_t)ldm);
 }
 
-// B_t (m x N) kept at every segment start of a checkpointed store.
+// B_t (m x N) and St (m x m) kept at every segment start of a checkpointed store.
 size_t bck_bytes(int64_t N, int64_t m, int64_t T, int stride) {
-    return stride > 1 ? 8 * (size_t)(T / stride + 1) * (size_t)m * round_up(N, 16) : 0;
+    return stride > 1 ? 8 * (size_t)(T / stride + 1) * (size_t)m * (round_up(N, 16) + round_up(m, 16)) : 0;
 }
 
 // Outer block width of the gain's factorisation for order N, and the leading dimension of the
@@ -264,13 +276,13 @@ size_t workspace_bytes(int64_t N, int64_t m, bool mix, bool s32, int stride, int
     size_t b = 0;
     b += 8 * (size_t)np * gb * gain_scratch_elems(N);
     b += 8 * (2 * NN + 2 * (size_t)m * ldN + (size_t)m * ldm + 2 * (size_t)N);   // Q, P0, X, XQ, R, x0
-    b += 8 * (2 * (size_t)m * ldN + 3 * (size_t)m * ldm + 3 * (size_t)N + 64);
+    b += 8 * (3 * (size_t)m * ldN + 7 * (size_t)m * ldm + 3 * (size_t)N + 64);   // B, two C, St, Sw, XQX, H, two Li, G
     b += 8 * (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);                 // split-K partials
     const size_t sets = (size_t)np + 1;
     b += 8 * ((2 * (size_t)np + sets) * (size_t)gb + 2) * NN;                // W, Li per stream, A per set; Ps x2
     if (!mix) b += 8 * 2 * NN;                                                   // D, M
     if (s32) b += 8 * sets * (size_t)gb * NN;                                    // upcast P_{t|t}
-    if (mix) b += 4 * (sets * (size_t)gb * NN + 2 * NN + (size_t)m * ldN);  // A32, D32, M32, Cm32
+    if (mix) b += 4 * (sets * (size_t)gb * NN + 2 * NN + 2 * (size_t)m * ldN);  // A32, D32, M32, two C32
     if (s32 || stride > 1) b += 8 * 2 * NN;
     if (mix) b += 4 * NN;
     if (stride > 1) b += (size_t)stride * NN * (s32 ? 4 : 8);
@@ -294,61 +306,35 @@ kf_status status_check(kf_plan* p, const char* phase) {
     return KF_OK;
 }
 
-// How filter step t obtains B_t = X P_{t|t-1}. With F = I, P_{t|t-1} = P_{t-1|t-1} + Q (eqn7) and
-// P_{t-1|t-1} = P_{t-1|t-2} - C_{t-1}^T C_{t-1} (the update after eqn10), so
-//     B_t = B_{t-1} + X Q - (X C_{t-1}^T) C_{t-1},
-// 4 m^2 N flops instead of 2 m N^2. The full product is taken every kBRefresh steps (and
-// always with a general F), which bounds the drift of the recursion. A recomputed segment of a
-// checkpointed store starts from the B_t kept at its first step, so that it reproduces the
-// forward pass bit for bit.
+// Filter step t (eqn8-eqn10 and the covariance update after eqn10) in four parts. With F = I,
+// P_{t+1|t} = P_{t|t-1} - C_t^T C_t + Q, and with St = X P_{t|t-1} X^T, S_t = St + R = L_t L_t^T,
+// C_t = L_t^{-1} X P_{t|t-1} and G_t = X C_t^T = St L_t^{-T}:
+//     St_{t+1} = St - G_t G_t^T + X Q X^T = R - R S_t^{-1} R + X Q X^T
+//              = X Q X^T + R - (L_t^{-1} R)^T (L_t^{-1} R),
+//     B_{t+1}  = B_t + X Q - G_t C_t,
+// (using St - St S_t^{-1} St = R - R S_t^{-1} R). So the chain from step to step is m x m work
+// only -- factor St + R, form H = L_t^{-1} R, St <- X Q X^T + R - H^T H -- and the Riccati form
+// does not accumulate rounding from step to step the way St - G G^T + X Q X^T would. The N-sized
+// work of step t -- C_t = L_t^{-1} B_t, the mean of eqn10, G_t = X C_t^T and B_{t+1}, and the
+// downdate P_t = P_pred - C_t^T C_t -- hangs off the chain and runs on side streams. B_t (whose
+// recursion does accumulate rounding) and St are formed in full every kBRefresh steps, and at
+// every step with a transition F, where the recursions do not hold; a checkpointed store keeps B_t
+// and St at every segment start, so that recomputed segments reproduce the forward pass bit for bit.
 constexpr int64_t kBRefresh = 16;
-enum BMode { B_FULL, B_RECUR, B_KEPT };
 
-BMode b_mode(const kf_plan* p, int64_t t) { return (p->hasF || t % kBRefresh == 0) ? B_FULL : B_RECUR; }
+bool refresh_step(const kf_plan* p, int64_t t) { return p->hasF || t % kBRefresh == 0; }
 
-// One covariance step of the filter from P_prev = P_{t-1|t-1} (or P0) to P_t; with `y`, also the mean.
-// Pout32 (optional) receives a float32 copy of P_t. `keep_b`: a checkpointed forward pass keeps
-// B_t at segment starts.
-kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* Pout64,
-                          float* Pout32, double* diag_out, const double* y, double* x_out_row,
-                          BMode bmode, bool keep_b) {
+// B_t = X P_{t|t-1} and St = B_t X^T in full from Pprev64 = P_{t-1|t-1} (or P0), on stream s.
+kf_status filter_refresh(kf_plan* p, const double* Pprev64, hipStream_t s) {
     const int N = (int)p->N, m = (int)p->m;
-    hipStream_t s = p->stream;
-    const size_t mN = (size_t)m * p->ldN;
-    // P_pred = P_prev + Q (F = I, never formed) or F P_prev F^T + Q (formed as F (P_prev F^T) + Q)
     const double* Ppred = nullptr;
-    if (p->hasF) {
+    if (p->hasF) {   // P_pred = F P_prev F^T + Q, formed as F (P_prev F^T) + Q
         HIPCK(dense_sparse_t(p->F, Pprev64, p->ldN, p->Fg, p->ldN, s));
         HIPCK(spmm_rows(p->F, p->Fg, p->ldN, 1.0, p->Q, p->ldN, 1.0, nullptr, 0, 0.0, p->Fp, false, p->ldN, s));
         Ppred = p->Fp;
     }
-    // B = X P_pred: with F = I, X P_prev + X Q. Float64 in both precisions: the gain and the
-    // mean depend on it through S^{-1}, where rounding is amplified by cond(S).
-    if (bmode == B_KEPT) {
-        HIPCK(hipMemcpyAsync(p->Bm, p->Bck + (size_t)(t / p->stride) * mN, mN * 8, hipMemcpyDeviceToDevice, s));
-    } else if (bmode == B_RECUR) {
-        {   // G = X C_{t-1}^T
-            GemmProblem g;
-            g.M = m; g.N = m; g.K = N;
-            g.A = p->X; g.lda = p->ldN;
-            g.B = p->Cm; g.ldb = p->ldN; g.flags = G_TB;
-            g.C = p->Gmm; g.ldc = p->ldm;
-            g.ksplit = std::max(1, std::min(32, N / 128));
-            g.partial = p->partial;
-            HIPCK(gemm1(Dt::F64, g, s));
-        }
-        {   // B_t = B_{t-1} + X Q - G C_{t-1}   (in place)
-            GemmProblem g;
-            g.M = m; g.N = N; g.K = m;
-            g.A = p->Gmm; g.lda = p->ldm;
-            g.B = p->Cm; g.ldb = p->ldN;
-            g.alpha = -1.0;
-            g.Cin = p->Bm; g.ldcin = p->ldN; g.beta = 1.0;
-            g.Cin2 = p->XQ; g.ldcin2 = p->ldN; g.gamma = 1.0;
-            g.C = p->Bm; g.ldc = p->ldN;
-            HIPCK(gemm1(Dt::F64, g, s));
-        }
-    } else {
+    {   // B = X P_pred; with F = I, X P_prev + X Q (float64 in both precisions: the gain and the mean
+        // depend on it through S^{-1}, where rounding is amplified by cond(S))
         GemmProblem g;
         g.M = m; g.N = N; g.K = N;
         g.ksplit = 4;
@@ -359,29 +345,60 @@ kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* 
         g.B = Ppred ? Ppred : Pprev64; g.ldb = p->ldN; g.flags = G_TB;   // P symmetric: read row-contiguous
         HIPCK(gemm1(Dt::F64, g, s));
     }
-    if (keep_b && p->stride > 1 && t % p->stride == 0)
-        HIPCK(hipMemcpyAsync(p->Bck + (size_t)(t / p->stride) * mN, p->Bm, mN * 8, hipMemcpyDeviceToDevice, s));
-    // S = B X^T + R
-    {
+    {   // St = B X^T
         GemmProblem g;
         g.M = m; g.N = m; g.K = N;
         g.A = p->Bm; g.lda = p->ldN;
         g.B = p->X; g.ldb = p->ldN; g.flags = G_TB;
-        g.Cin = p->R; g.ldcin = p->ldm; g.beta = 1.0;
-        g.C = p->S; g.ldc = p->ldm;
+        g.C = p->St; g.ldc = p->ldm;
         g.ksplit = std::max(1, std::min(32, N / 128));
         g.partial = p->partial;
         HIPCK(gemm1(Dt::F64, g, s));
     }
-    HIPCK(chol_inv(p->S, p->ldm, p->Lis, p->ldm, m, p->dstatus, W_S, (int)t + 1, s));
-    // C = Li B
+    return KF_OK;
+}
+
+// The m x m chain of step t on stream s: factor S_t = St + R (eqn8), L_t^{-1} into slot t & 1;
+// then, unless step t + 1 forms St in full, St <- X Q X^T + R - H^T H with H = L_t^{-1} R.
+kf_status filter_mchain(kf_plan* p, int64_t t, int64_t T, hipStream_t s) {
+    const int m = (int)p->m;
+    HIPCK(axpby3(m, m, p->Sw, false, p->ldm, p->St, false, p->ldm, p->R, false, p->ldm, 1.0, nullptr, false, 0, 0.0,
+                 s));
+    HIPCK(chol_inv(p->Sw, p->ldm, p->Li2[t & 1], p->ldm, m, p->dstatus, W_S, (int)t + 1, s));
+    if (t + 1 >= T || refresh_step(p, t + 1)) return KF_OK;
+    {   // H = L_t^{-1} R
+        GemmProblem g;
+        g.M = m; g.N = m; g.K = m;
+        g.A = p->Li2[t & 1]; g.lda = p->ldm; g.flags = G_ALOWER;
+        g.B = p->R; g.ldb = p->ldm;
+        g.C = p->Hm; g.ldc = p->ldm;
+        HIPCK(gemm1(Dt::F64, g, s));
+    }
+    {   // St <- X Q X^T + R - H^T H   (lower tiles + mirror)
+        GemmProblem g;
+        g.M = m; g.N = m; g.K = m;
+        g.A = p->Hm; g.lda = p->ldm; g.flags = G_TA | G_LOWER | G_MIRROR;
+        g.B = p->Hm; g.ldb = p->ldm;
+        g.alpha = -1.0;
+        g.Cin = p->XQX; g.ldcin = p->ldm; g.beta = 1.0;
+        g.Cin2 = p->R; g.ldcin2 = p->ldm; g.gamma = 1.0;
+        g.C = p->St; g.ldc = p->ldm;
+        HIPCK(gemm1(Dt::F64, g, s));
+    }
+    return KF_OK;
+}
+
+// C_t = L_t^{-1} B_t into slot t & 1 (and its float32 copy for the mixed downdate), then, with `y`,
+// the mean of eqn10: x_t = x_pred + C_t^T (L_t^{-1} (y_t - X x_pred)).
+kf_status filter_gain_mean(kf_plan* p, int64_t t, const double* y, double* x_out_row, hipStream_t s) {
+    const int N = (int)p->N, m = (int)p->m;
     {
         GemmProblem g;
         g.M = m; g.N = N; g.K = m;
-        g.A = p->Lis; g.lda = p->ldm; g.flags = G_ALOWER;
+        g.A = p->Li2[t & 1]; g.lda = p->ldm; g.flags = G_ALOWER;
         g.B = p->Bm; g.ldb = p->ldN;
-        g.C = p->Cm; g.ldc = p->ldN;
-        if (mixed(p)) { g.C32 = p->Cm32; g.ldc32 = p->ldN; }
+        g.C = p->Cm2[t & 1]; g.ldc = p->ldN;
+        if (mixed(p)) { g.C32 = p->Cm32x[t & 1]; g.ldc32 = p->ldN; }
         HIPCK(gemm1(Dt::F64, g, s));
     }
     if (y) {
@@ -391,29 +408,97 @@ kf_status filter_cov_step(kf_plan* p, int64_t t, const double* Pprev64, double* 
             xpred = p->xp;
         }
         HIPCK(resid(p->X, p->ldN, xpred, y, p->e, m, N, s));
-        HIPCK(trmv_lower(p->Lis, p->ldm, p->e, p->w, m, s));
-        HIPCK(gemv_t_add(p->Cm, p->ldN, p->w, xpred, p->xw, x_out_row, m, N, s));
-    }
-    // P_t = P_prev + Q - C^T C
-    {
-        GemmProblem g;
-        g.M = N; g.N = N; g.K = m;
-        g.flags = G_TA | G_LOWER | G_MIRROR;
-        g.alpha = -1.0;
-        g.Cin = Ppred ? Ppred : Pprev64; g.ldcin = p->ldN; g.beta = 1.0;
-        if (!Ppred) { g.Cin2 = p->Q; g.ldcin2 = p->ldN; g.gamma = 1.0; }
-        g.C = Pout64; g.ldc = p->ldN;
-        g.C32 = Pout32; g.ldc32 = p->ldN;
-        g.diag = diag_out;
-        if (mixed(p)) {
-            g.A = p->Cm32; g.lda = p->ldN; g.B = p->Cm32; g.ldb = p->ldN;
-            HIPCK(gemm1(Dt::F32, g, s));
-        } else {
-            g.A = p->Cm; g.lda = p->ldN; g.B = p->Cm; g.ldb = p->ldN;
-            HIPCK(gemm1(Dt::F64, g, s));
-        }
+        HIPCK(trmv_lower(p->Li2[t & 1], p->ldm, p->e, p->w, m, s));
+        HIPCK(gemv_t_add(p->Cm2[t & 1], p->ldN, p->w, xpred, p->xw, x_out_row, m, N, s));
     }
     return KF_OK;
+}
+
+// G_t = X C_t^T, then B_{t+1} = B_t + X Q - G_t C_t in place (a recursive step t + 1 only).
+kf_status filter_b_update(kf_plan* p, int64_t t, hipStream_t s) {
+    const int N = (int)p->N, m = (int)p->m;
+    {
+        GemmProblem g;
+        g.M = m; g.N = m; g.K = N;
+        g.A = p->X; g.lda = p->ldN;
+        g.B = p->Cm2[t & 1]; g.ldb = p->ldN; g.flags = G_TB;
+        g.C = p->Gm; g.ldc = p->ldm;
+        g.ksplit = std::max(1, std::min(32, N / 128));
+        g.partial = p->partial;
+        HIPCK(gemm1(Dt::F64, g, s));
+    }
+    GemmProblem g;
+    g.M = m; g.N = N; g.K = m;
+    g.A = p->Gm; g.lda = p->ldm;
+    g.B = p->Cm2[t & 1]; g.ldb = p->ldN;
+    g.alpha = -1.0;
+    g.Cin = p->Bm; g.ldcin = p->ldN; g.beta = 1.0;
+    g.Cin2 = p->XQ; g.ldcin2 = p->ldN; g.gamma = 1.0;
+    g.C = p->Bm; g.ldc = p->ldN;
+    HIPCK(gemm1(Dt::F64, g, s));
+    return KF_OK;
+}
+
+// B_t and St at a segment start of a checkpointed store: keep them (forward pass) or restore them.
+kf_status filter_keep_state(kf_plan* p, int64_t t, bool restore, hipStream_t sb, hipStream_t ss) {
+    const size_t mN = (size_t)p->m * p->ldN, mm = (size_t)p->m * p->ldm;
+    const int64_t k = t / p->stride;
+    double* bk = p->Bck + (size_t)k * mN;
+    double* sk = p->Sck + (size_t)k * mm;
+    HIPCK(hipMemcpyAsync(restore ? p->Bm : bk, restore ? bk : p->Bm, mN * 8, hipMemcpyDeviceToDevice, sb));
+    HIPCK(hipMemcpyAsync(restore ? p->St : sk, restore ? sk : p->St, mm * 8, hipMemcpyDeviceToDevice, ss));
+    return KF_OK;
+}
+
+// Lower tiles of the downdate run in launches of at most this many workgroups when it overlaps
+// other work, leaving compute units free for the filter's small kernels.
+constexpr int kDowndateChunk = 288;
+
+// The covariance update after eqn10 for step t on stream `s`: P_t = P_pred - C_t^T C_t with
+// P_pred = P_prev + Q (F = I) or the F P_prev F^T + Q that filter_refresh formed; lower tiles
+// with a mirrored store (exact symmetry), the diagonal to diag_out, float64 to Pout64 and
+// (optional) float32 to Pout32. `chunked`: in launches of at most kDowndateChunk workgroups (the
+// tiles, and so the result, are the same either way).
+kf_status filter_downdate(kf_plan* p, int64_t t, const double* Pprev64, double* Pout64, float* Pout32,
+                          double* diag_out, hipStream_t s, bool chunked) {
+    const int N = (int)p->N, m = (int)p->m;
+    const double* Ppred = p->hasF ? p->Fp : nullptr;
+    GemmProblem g;
+    g.M = N; g.N = N; g.K = m;
+    g.flags = G_TA | G_LOWER | G_MIRROR;
+    g.alpha = -1.0;
+    g.Cin = Ppred ? Ppred : Pprev64; g.ldcin = p->ldN; g.beta = 1.0;
+    if (!Ppred) { g.Cin2 = p->Q; g.ldcin2 = p->ldN; g.gamma = 1.0; }
+    g.C = Pout64; g.ldc = p->ldN;
+    g.C32 = Pout32; g.ldc32 = p->ldN;
+    g.diag = diag_out;
+    const Dt dt = mixed(p) ? Dt::F32 : Dt::F64;
+    if (mixed(p)) { g.A = p->Cm32x[t & 1]; g.B = p->Cm32x[t & 1]; }
+    else { g.A = p->Cm2[t & 1]; g.B = p->Cm2[t & 1]; }
+    g.lda = g.ldb = p->ldN;
+    const int tiles = gemm_tiles(g);
+    const int chunk = chunked ? kDowndateChunk : tiles;
+    for (int off = 0; off < tiles; off += chunk) {
+        GemmProblem h = g;
+        h.tile_off = off;
+        h.tile_cnt = std::min(chunk, tiles - off);
+        HIPCK(gemm1(dt, h, s));
+    }
+    return KF_OK;
+}
+
+// One covariance step of the filter, everything on the plan's stream (recomputation of a
+// checkpointed segment; no mean). `restore`: step t starts a recomputed segment whose B_t and
+// St were kept by the forward pass.
+kf_status filter_cov_step(kf_plan* p, int64_t t, int64_t T, const double* Pprev64, double* Pout64, float* Pout32,
+                          bool restore) {
+    hipStream_t s = p->stream;
+    if (refresh_step(p, t)) TRY(filter_refresh(p, Pprev64, s));
+    else if (restore) TRY(filter_keep_state(p, t, true, s, s));
+    TRY(filter_mchain(p, t, T, s));
+    TRY(filter_gain_mean(p, t, nullptr, nullptr, s));
+    if (t + 1 < T && !refresh_step(p, t + 1)) TRY(filter_b_update(p, t, s));
+    return filter_downdate(p, t, Pprev64, Pout64, Pout32, nullptr, s, false);
 }
 
 // Buffers for the means of B data sets (E, W: B x m residuals; Xb0: B copies of x0; Vb: B x N).
@@ -446,12 +531,11 @@ int batch_ksplit(const kf_plan* p, int64_t rows, int64_t cols, int want) {
     return k;
 }
 
-// Mean update of eqn10 for B data sets at once, after filter_cov_step(t) has left Li = L^{-1}
-// (of S_t) and C = Li X P_{t|t-1} in the plan: with E = Y_t - X_prev X^T (B x m),
+// Mean update of eqn10 for B data sets at once, after filter_chain_step(t) has left Li = L^{-1}
+// (of S_t) and C_t = Li X P_{t|t-1} in the plan: with E = Y_t - X_prev X^T (B x m),
 // X_t = X_prev + (E Li^T) C. Row b of X_prev / X_t is data set b's mean (leading dimension ldx).
-kf_status filter_mean_batch(kf_plan* p, int64_t B, const double* Xprev, int64_t ldprev, const double* Yt,
-                            int64_t ldy, double* Xt, int64_t ldx) {
-    hipStream_t s = p->stream;
+kf_status filter_mean_batch(kf_plan* p, int64_t t, int64_t B, const double* Xprev, int64_t ldprev, const double* Yt,
+                            int64_t ldy, double* Xt, int64_t ldx, hipStream_t s) {
     const int N = (int)p->N, m = (int)p->m;
     if (p->hasF) {                           // predicted means F x (eqn6)
         HIPCK(spmv_rows(p->F, Xprev, ldprev, (int)B, p->Ub, p->ldN, s));
@@ -474,7 +558,7 @@ kf_status filter_mean_batch(kf_plan* p, int64_t B, const double* Xprev, int64_t 
         GemmProblem g;                       // W = E Li^T  (Li lower: W_b = Li e_b)
         g.M = (int)B; g.N = m; g.K = m;
         g.A = p->Eb; g.lda = p->ldm;
-        g.B = p->Lis; g.ldb = p->ldm; g.flags = G_TB;
+        g.B = p->Li2[t & 1]; g.ldb = p->ldm; g.flags = G_TB;
         g.C = p->Wb; g.ldc = p->ldm;
         HIPCK(gemm1(Dt::F64, g, s));
     }
@@ -482,7 +566,7 @@ kf_status filter_mean_batch(kf_plan* p, int64_t B, const double* Xprev, int64_t 
         GemmProblem g;                       // X_t = X_prev + W C
         g.M = (int)B; g.N = N; g.K = m;
         g.A = p->Wb; g.lda = p->ldm;
-        g.B = p->Cm; g.ldb = p->ldN;
+        g.B = p->Cm2[t & 1]; g.ldb = p->ldN;
         g.Cin = Xprev; g.ldcin = ldprev; g.beta = 1.0;
         g.C = Xt; g.ldc = ldx;
         HIPCK(gemm1(Dt::F64, g, s));
@@ -675,8 +759,13 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
 #define ALLOC(ptr, n)                        \
     if ((st = alloc(p, &(ptr), (n))) != KF_OK) return fail(st);
     ALLOC(p->X, mN); ALLOC(p->XQ, mN); ALLOC(p->Q, NN); ALLOC(p->R, mm); ALLOC(p->x0, (size_t)N); ALLOC(p->P0, NN);
-    ALLOC(p->Bm, mN); ALLOC(p->Cm, mN); ALLOC(p->S, mm); ALLOC(p->Lis, mm); ALLOC(p->Gmm, mm);
-    if (stride > 1) ALLOC(p->Bck, (size_t)(T_max / stride + 1) * mN);
+    ALLOC(p->Bm, mN); ALLOC(p->Cm2[0], mN); ALLOC(p->Cm2[1], mN);
+    ALLOC(p->St, mm); ALLOC(p->Sw, mm); ALLOC(p->XQX, mm); ALLOC(p->Hm, mm);
+    ALLOC(p->Li2[0], mm); ALLOC(p->Li2[1], mm); ALLOC(p->Gm, mm);
+    if (stride > 1) {
+        ALLOC(p->Bck, (size_t)(T_max / stride + 1) * mN);
+        ALLOC(p->Sck, (size_t)(T_max / stride + 1) * mm);
+    }
     ALLOC(p->e, (size_t)m); ALLOC(p->w, (size_t)m); ALLOC(p->xw, (size_t)N);
     p->partial_elems = (size_t)std::max<int64_t>(4 * m * N, 32 * m * m);
     ALLOC(p->partial, p->partial_elems);
@@ -706,7 +795,7 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     }
     if (!mix) { ALLOC(p->Dm, NN); ALLOC(p->Mm, NN); }
     if (mix) {
-        ALLOC(p->Cm32, mN);
+        ALLOC(p->Cm32x[0], mN); ALLOC(p->Cm32x[1], mN);
         ALLOC(p->D32, NN); ALLOC(p->M32, NN);
     }
     if (p->store32 || stride > 1) { ALLOC(p->Pw[0], NN); ALLOC(p->Pw[1], NN); }
@@ -737,6 +826,9 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
         for (int k = 0; ok && k <= p->nprod; ++k)
             ok = hipEventCreateWithFlags(&p->ev_gain[k], hipEventDisableTiming) == hipSuccess &&
                  hipEventCreateWithFlags(&p->ev_chain[k], hipEventDisableTiming) == hipSuccess;
+        for (int k = 0; ok && k < 2; ++k)
+            for (hipEvent_t* e : {&p->ev_fl[k], &p->ev_fg[k], &p->ev_fr[k], &p->ev_fa[k], &p->ev_cc[k], &p->ev_dd[k]})
+                ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
         if (!ok) {
             p->err = "kf_create: creating the side streams or their events failed";
             return fail(KF_EHIP);
@@ -757,8 +849,12 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
         g.M = (int)m; g.N = (int)N; g.K = (int)N;
         g.A = p->X; g.lda = p->ldN; g.B = p->Q; g.ldb = p->ldN;
         g.C = p->XQ; g.ldc = p->ldN;
-        if (gemm1(Dt::F64, g, s) != hipSuccess) {
-            p->err = "kf_create: forming X Q failed";
+        GemmProblem h;                           // X Q X^T, used by the recursion of St
+        h.M = (int)m; h.N = (int)m; h.K = (int)N;
+        h.A = p->XQ; h.lda = p->ldN; h.B = p->X; h.ldb = p->ldN; h.flags = G_TB;
+        h.C = p->XQX; h.ldc = p->ldm;
+        if (gemm1(Dt::F64, g, s) != hipSuccess || gemm1(Dt::F64, h, s) != hipSuccess) {
+            p->err = "kf_create: forming X Q and X Q X^T failed";
             return fail(KF_EHIP);
         }
     }
@@ -825,32 +921,74 @@ static kf_status filter_impl(kf_plan* p, int64_t B, int64_t T, const double* Y, 
         HIPCK(copy2d((int)B, (int)N, p->Xb0, false, p->ldN, p->x0, false, 0, s));   // x0 in every row
     }
     const bool direct = !p->store32 && p->stride == 1;   // store slot t is the working P
+    // Streams: the m x m chain on the plan's stream s; the N-sized work of each step (C_t, the mean,
+    // B's recursion and refreshes) on sa; the downdates on sd (= sa with one side stream). Slot
+    // t & 1 of L^{-1} and C is reused at step t + 2, after the streams that read it at step t.
+    hipStream_t sa = p->s2[0], sd = p->nprod > 1 ? p->s2[1] : p->s2[0];
+    HIPCK(hipEventRecord(p->ev_start, s));
+    HIPCK(hipStreamWaitEvent(sa, p->ev_start, 0));
+    if (sd != sa) HIPCK(hipStreamWaitEvent(sd, p->ev_start, 0));
     const double* prev64 = p->P0;
     for (int64_t t = 0; t < T; ++t) {
         Range r("kf_filter step t=%lld", (long long)t + 1);
-        double* out64 = direct ? static_cast<double*>(slot_ptr(p, t)) : p->Pw[t & 1];
+        const int k = (int)(t & 1);
+        double* out64 = direct ? static_cast<double*>(slot_ptr(p, t)) : p->Pw[k];
         float* out32 = nullptr;
         if (!slot64(p) && kept(p, t, T)) out32 = static_cast<float*>(slot_ptr(p, slot_of(p, t, T)));
         double* diag = Pdiag ? Pdiag + t * N : nullptr;
-        if (B == 1) {
-            TRY(filter_cov_step(p, t, prev64, out64, out32, diag, Y + t * m, x_filt + t * N, b_mode(p, t), true));
-        } else {
-            TRY(filter_cov_step(p, t, prev64, out64, out32, diag, nullptr, nullptr, b_mode(p, t), true));
-            const double* xprev = t == 0 ? p->Xb0 : x_filt + (t - 1) * N;
-            TRY(filter_mean_batch(p, B, xprev, t == 0 ? p->ldN : T * N, Y + t * m, T * m, x_filt + t * N, T * N));
+        const bool full = refresh_step(p, t);
+        const bool seg = p->stride > 1 && t % p->stride == 0;
+        // N side: refresh B_t and St from P_{t-1|t-1} (after downdate t - 1)
+        if (full) {
+            if (t >= 1) HIPCK(hipStreamWaitEvent(sa, p->ev_dd[k ^ 1], 0));
+            TRY(filter_refresh(p, prev64, sa));
         }
+        if (seg) {                                        // segment start: keep B_t and St
+            if (!full) HIPCK(hipStreamWaitEvent(sa, p->ev_fg[k ^ 1], 0));   // St_t was formed on s
+            TRY(filter_keep_state(p, t, false, sa, sa));
+        }
+        if (full || seg) {                                // s reads (and later overwrites) St after these
+            HIPCK(hipEventRecord(p->ev_fr[k], sa));
+            HIPCK(hipStreamWaitEvent(s, p->ev_fr[k], 0));
+        }
+        // m x m chain: L_t^{-1}, G_t, St_{t+1}
+        if (t >= 2) HIPCK(hipStreamWaitEvent(s, p->ev_fa[k], 0));            // step t - 2 done with slot k
+        TRY(filter_mchain(p, t, T, s));
+        HIPCK(hipEventRecord(p->ev_fg[k], s));
+        // N side of step t: C_t (slot k, read by downdate t - 2 before), the mean, B_{t+1}
+        HIPCK(hipStreamWaitEvent(sa, p->ev_fg[k], 0));
+        if (t >= 2) HIPCK(hipStreamWaitEvent(sa, p->ev_dd[k], 0));
+        if (B == 1) {
+            TRY(filter_gain_mean(p, t, Y + t * m, x_filt + t * N, sa));
+        } else {
+            TRY(filter_gain_mean(p, t, nullptr, nullptr, sa));
+            const double* xprev = t == 0 ? p->Xb0 : x_filt + (t - 1) * N;
+            TRY(filter_mean_batch(p, t, B, xprev, t == 0 ? p->ldN : T * N, Y + t * m, T * m, x_filt + t * N,
+                                  T * N, sa));
+        }
+        HIPCK(hipEventRecord(p->ev_cc[k], sa));
+        if (p->keep) {   // C_t, L_t^-1 and L_t^-1 e_t (one row per data set) for the mean-only smoother
+            HIPCK(hipMemcpyAsync(p->fac_C + t * m * p->ldN, p->Cm2[k], (size_t)m * p->ldN * 8,
+                                 hipMemcpyDeviceToDevice, sa));
+            HIPCK(hipMemcpyAsync(p->fac_L + t * m * p->ldm, p->Li2[k], (size_t)m * p->ldm * 8,
+                                 hipMemcpyDeviceToDevice, sa));
+            HIPCK(hipMemcpyAsync(p->fac_w + t * p->wcap * p->ldm, B == 1 ? p->w : p->Wb,
+                                 (B == 1 ? (size_t)m : (size_t)B * p->ldm) * 8, hipMemcpyDeviceToDevice, sa));
+        }
+        if (t + 1 < T && !refresh_step(p, t + 1)) TRY(filter_b_update(p, t, sa));
+        HIPCK(hipEventRecord(p->ev_fa[k], sa));
+        // downdate of step t
+        if (sd != sa) HIPCK(hipStreamWaitEvent(sd, p->ev_cc[k], 0));
+        TRY(filter_downdate(p, t, prev64, out64, out32, diag, sd, true));
         if (!direct && slot64(p) && kept(p, t, T)) {
             HIPCK(hipMemcpyAsync(slot_ptr(p, slot_of(p, t, T)), out64, slot_elems(p) * 8, hipMemcpyDeviceToDevice,
-                                 s));
+                                 sd));
         }
-        if (p->keep) {   // C_t, L_t^-1 and L_t^-1 e_t (one row per data set) for the mean-only smoother
-            HIPCK(hipMemcpyAsync(p->fac_C + t * m * p->ldN, p->Cm, (size_t)m * p->ldN * 8, hipMemcpyDeviceToDevice, s));
-            HIPCK(hipMemcpyAsync(p->fac_L + t * m * p->ldm, p->Lis, (size_t)m * p->ldm * 8, hipMemcpyDeviceToDevice, s));
-            HIPCK(hipMemcpyAsync(p->fac_w + t * p->wcap * p->ldm, B == 1 ? p->w : p->Wb,
-                                 (B == 1 ? (size_t)m : (size_t)B * p->ldm) * 8, hipMemcpyDeviceToDevice, s));
-        }
+        HIPCK(hipEventRecord(p->ev_dd[k], sd));
         prev64 = out64;
     }
+    HIPCK(hipStreamWaitEvent(s, p->ev_fa[(T - 1) & 1], 0));
+    HIPCK(hipStreamWaitEvent(s, p->ev_dd[(T - 1) & 1], 0));
     return sync_and_check(p, "kf_filter");
 }
 
@@ -898,8 +1036,7 @@ kf_status recompute_segment(kf_plan* p, int64_t t0, int64_t t1, int64_t T) {
         double* out64 = p->Pw[(t - t0 + 1) & 1];
         void* segslot = static_cast<char*>(p->seg) + (size_t)(t - t0) * slot_elems(p) * esz;
         float* out32 = s32 ? static_cast<float*>(segslot) : nullptr;
-        const BMode bm = (t == t0 && b_mode(p, t) == B_RECUR) ? B_KEPT : b_mode(p, t);
-        TRY(filter_cov_step(p, t, prev64, out64, out32, nullptr, nullptr, nullptr, bm, false));
+        TRY(filter_cov_step(p, t, T, prev64, out64, out32, t == t0));
         if (!s32) HIPCK(hipMemcpyAsync(segslot, out64, slot_elems(p) * 8, hipMemcpyDeviceToDevice, s));
         prev64 = out64;
     }
@@ -1630,6 +1767,9 @@ void kf_destroy(kf_plan* p) {
         if (p->ev_gain[k]) (void)hipEventDestroy(p->ev_gain[k]);
         if (p->ev_chain[k]) (void)hipEventDestroy(p->ev_chain[k]);
     }
+    for (int k = 0; k < 2; ++k)
+        for (hipEvent_t e : {p->ev_fl[k], p->ev_fg[k], p->ev_fr[k], p->ev_fa[k], p->ev_cc[k], p->ev_dd[k]})
+            if (e) (void)hipEventDestroy(e);
     for (hipStream_t q : p->s2)
         if (q) (void)hipStreamDestroy(q);
     for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb, p->Ub})
