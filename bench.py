@@ -235,12 +235,13 @@ def path_roofline(p, ms_pass):
 
 
 def mixed_roofline(p, ms_pass):
-    """Mixed-precision bound of one pass: the float64 work (Cholesky of S and of P_{t+1|t}, the
-    two gain products) at the FP64 peak plus the float32 work (X P, S, C^T C; eqn13's M = A_t D
-    and P_t + M A_t^T) at the FP32 peak, against the measured pass."""
+    """Mixed-precision bound of one pass: the float64 work (X P, S, the Cholesky of S, C = L^{-1} B;
+    the Cholesky of P_{t+1|t} and the two gain solves) at the FP64 peak plus the float32 work (the
+    downdate C^T C; eqn13's M = A_t D and P_t + M A_t^T) at the FP32 peak, against the measured
+    pass."""
     N, m, T = p.N, p.m, p.T
-    f64 = T * m ** 3 / 3.0 + (T - 1) * (N ** 3 / 3.0 + 2.0 * N ** 3)
-    f32 = T * (3.0 * m * N * N + 3.0 * m * m * N) + (T - 1) * 3.0 * N ** 3
+    f64 = T * (2.0 * m * N * N + 2.0 * m * m * N + m ** 3 / 3.0 + m * m * N) + (T - 1) * (N ** 3 / 3.0 + 2.0 * N ** 3)
+    f32 = T * m * N * N + (T - 1) * 3.0 * N ** 3
     bound_ms = (f64 / PEAK_F64 + f32 / PEAK_F32) * 1e3
     return {"f64_flops_per_pass": f64, "f32_flops_per_pass": f32, "bound_ms_per_pass": bound_ms,
             "measured_ms_per_pass": ms_pass, "frac": bound_ms / ms_pass}

@@ -4,6 +4,7 @@
     python -m paper_1107_4192_amd.profiling traffic <fetch counter csv> <write counter csv> <kernel> <out.json> \
         [bench log of the counter run]
     python -m paper_1107_4192_amd.profiling mfma <counter csv> <kernel trace csv> [min_ms]
+    python -m paper_1107_4192_amd.profiling isolated <kernel trace csv> [steps]
 
 ``traffic`` scales the per-dispatch FETCH_SIZE and WRITE_SIZE of `kernel` by what
 the same counters read for the plain 256 MiB device copy that ``bench.py
@@ -113,6 +114,34 @@ def mfma_busy(counter_csv: str, trace_csv: str, min_ms: float = 1.0) -> str:
     return "\n".join(lines)
 
 
+def isolated_pass(trace_csv: str, steps: int = 199) -> str:
+    """Kernel time of the smoother pass that ``bench.py`` serialises onto one stream (the pass whose
+    eqn13 products run as gemm_kernel<double, 3, *>): per kernel, summed over the pass and per step.
+    The pass starts at the first kernel after the preceding filter's last covariance update."""
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    marks = [i for i, r in enumerate(rows) if "gemm_kernel<double, 3," in r["Kernel_Name"]]
+    if not marks:
+        raise ValueError("no serialised smoother pass in this trace")
+    t1 = int(rows[marks[-1]]["End_Timestamp"])
+    i0 = marks[0]
+    # walk back to the end of the filter pass before it: the last float64 TN launch (the downdate)
+    while i0 > 0 and "gemm_kernel<double, 0, 2>" not in rows[i0 - 1]["Kernel_Name"]:
+        i0 -= 1
+    win = [r for r in rows[i0:] if int(r["End_Timestamp"]) <= t1]
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for r in win:
+        n = r["Kernel_Name"].replace("kfmeg::", "").replace("(anonymous namespace)::", "").split("(")[0]
+        agg[n][0] += 1
+        agg[n][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+    wall = (t1 - int(win[0]["Start_Timestamp"])) * 1e-6
+    tot = sum(v[1] for v in agg.values())
+    lines = [f"pass {wall:.1f} ms, summed kernel time {tot:.1f} ms, gaps {wall - tot:.1f} ms",
+             f"{'kernel':60s} {'launches':>8s} {'total_ms':>9s} {'ms/step':>8s}"]
+    for n, (c, ms) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{n[:60]:60s} {c:8d} {ms:9.1f} {ms / steps:8.3f}")
+    return "\n".join(lines)
+
+
 def main(argv):
     if argv[1] == "stats":
         print(kernel_stats_summary(argv[2], int(argv[3]) if len(argv) > 3 else 15))
@@ -123,6 +152,8 @@ def main(argv):
         print(json.dumps({k: v for k, v in d.items() if k != "per_dispatch_bytes"}, indent=1))
     elif argv[1] == "mfma":
         print(mfma_busy(argv[2], argv[3], float(argv[4]) if len(argv) > 4 else 1.0))
+    elif argv[1] == "isolated":
+        print(isolated_pass(argv[2], int(argv[3]) if len(argv) > 3 else 199))
     else:
         raise SystemExit(__doc__)
 
