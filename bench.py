@@ -388,11 +388,40 @@ def run_batched(p, B, steps):
             "s_per_pass": elapsed / steps}
 
 
+def fp64_step_times(shapes, T_probe=8):
+    """Seconds per time step (filter + smoother) of a plain FP64 job of each (N, m) shape, from a
+    short job run twice (the second run timed)."""
+    import numpy as np
+    import torch
+    from paper_1107_4192_amd import kfmeg, synth
+
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    out = {}
+    for (N, m) in shapes:
+        p = synth.custom(4242, N, m, T_probe)
+        arrs = tuple(dev(a) for a in (p.X, p.Q, p.R, p.x0, p.P0, p.Y))
+        ks = kfmeg.KalmanSmoother(*arrs[:5], T_max=T_probe)
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ks.run(arrs[5])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        ks.close()
+        del arrs
+        out[(N, m)] = dt / T_probe
+        log(f"FP64 probe N={N} m={m}: {dt / T_probe * 1e3:.1f} ms per step")
+    return out
+
+
 def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(102, 204, 306),
-                T_range=(20, 60), max_active=4, budget_gib=0.0, plan=None):
+                T_range=(20, 60), max_active=4, budget_gib=0.0, plan=None, estimate_baseline=False):
     """Serving form: Poisson arrivals of filter+smoother jobs of mixed shapes, mixed precision
     with float32 stores, continuously batched; against the same jobs one at a time in FP64.
-    `plan` replaces the drawn stream with an explicit job list (arrival_s, N, m, T, seed)."""
+    `plan` replaces the drawn stream with an explicit job list (arrival_s, N, m, T, seed).
+    `estimate_baseline`: instead of running the jobs one at a time in FP64, time a short FP64 job
+    of each shape and sum T x seconds per step over the jobs (for streams whose sequential FP64 run
+    would take tens of minutes)."""
     import numpy as np
     import torch
     from paper_1107_4192_amd import kfmeg, synth
@@ -417,32 +446,50 @@ def run_serving(n_jobs=16, seed=5, rate=4.0, N_choices=(2000, 5124), m_choices=(
         if delay > 0:
             time.sleep(delay)
         ids.append(srv.submit(*arrs))
-    for i in ids:
-        srv.wait(i)
+    # collect each job as it completes (a line per job: long streams stay visibly alive)
+    lat, pending = {}, list(ids)
+    while pending:
+        for i in [i for i in pending if srv.info(i)["done"]]:
+            lat[i] = srv.wait(i)[2]
+            pending.remove(i)
+            log(f"serving: job {ids.index(i)} done, latency {lat[i]:.0f} ms ({len(ids) - len(pending)}/{len(ids)})")
+        if pending:
+            time.sleep(0.05)
+    lats = [lat[i] for i in ids]
     st = srv.stats()
     infos = [srv.info(i) for i in ids]
     srv.close()
     log(f"serving: {st['completed']} jobs, p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms, "
         f"{st['checkpointed']} checkpointed")
-    # baseline: the same jobs one at a time in plain FP64
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for j, arrs in jobs:
-        ks = kfmeg.KalmanSmoother(*arrs[:5], T_max=j["T"])
-        ks.run(arrs[5])
-        ks.close()
-    torch.cuda.synchronize()
-    seq = time.perf_counter() - t0
-    steps = sum(j["T"] for j, _ in jobs)
-    log(f"serving: sequential FP64 {seq:.1f} s")
     shapes = sorted({(j["N"], j["m"]) for j in plan})
-    return {"workload": f"{len(jobs)} jobs, N x m in {shapes}, T in [{min(j['T'] for j in plan)}, "
+    steps = sum(j["T"] for j, _ in jobs)
+    if estimate_baseline:
+        del jobs[:]
+        torch.cuda.empty_cache()
+        per_step = fp64_step_times(shapes)
+        seq = sum(j["T"] * per_step[(j["N"], j["m"])] for j in plan)
+        log(f"serving: sequential FP64 estimated at {seq:.1f} s")
+    else:
+        # baseline: the same jobs one at a time in plain FP64
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j, arrs in jobs:
+            ks = kfmeg.KalmanSmoother(*arrs[:5], T_max=j["T"])
+            ks.run(arrs[5])
+            ks.close()
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t0
+        log(f"serving: sequential FP64 {seq:.1f} s")
+    return {"workload": f"{len(plan)} jobs, N x m in {shapes}, T in [{min(j['T'] for j in plan)}, "
                         f"{max(j['T'] for j in plan)}], arrivals over {plan[-1]['arrival_s']:.1f} s; mixed "
                         "precision, float32 store" + (f", HBM budget {budget_gib:g} GiB" if budget_gib else ""),
             "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "jobs_per_s": st["jobs_per_s"],
             "steps_per_s": st["steps_per_s"], "max_concurrent": st["max_concurrent"],
             "checkpointed": st["checkpointed"], "peak_gib": st["peak_bytes"] / 2 ** 30,
             "sequential_fp64_steps_per_s": steps / seq,
+            "sequential_fp64": "estimated from a short FP64 job per shape" if estimate_baseline else "measured",
+            "jobs": [(j["N"], j["m"], j["T"], round(j["arrival_s"], 3)) for j in plan],
+            "latency_ms": [round(v, 1) for v in lats],
             "throughput_speedup_vs_sequential_fp64": st["steps_per_s"] / (steps / seq),
             "mean_queue_ms": float(np.mean([i["queued_ms"] for i in infos])),
             "checkpoint_strides": [i["checkpoint_stride"] for i in infos]}
@@ -513,7 +560,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-free", action="store_true", help="skip the free-orientation leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the mean-only, batched and associative-scan legs")
-    ap.add_argument("--workload", choices=("paper", "free", "serving"), default="paper",
+    ap.add_argument("--jobs", type=int, default=64, help="jobs of the 64-job stream run by --workload serving5")
+    ap.add_argument("--workload", choices=("paper", "free", "serving", "serving5"), default="paper",
                     help="free: the free-orientation N=15372 workload only (full store and checkpointed); "
                          "serving: a larger serving run only (48 jobs up to N=8196 under a 96 GiB budget)")
     args = ap.parse_args()
@@ -531,6 +579,13 @@ def main():
 
     if args.workload == "free":
         print(json.dumps({"free_orientation": run_free(T=min(args.T, 100))}), flush=True)
+        return
+    if args.workload == "serving5":
+        # the 64-job stream of mixed N (2000 to 15372), m and T (50 to 400) at 4 arrivals/s; the
+        # first --jobs of it, in arrival order
+        plan = synth.serving_jobs(seed=5, n_jobs=64)[:args.jobs]
+        print(json.dumps({"serving_stream64": run_serving(plan=plan, max_active=4, estimate_baseline=True)}),
+              flush=True)
         return
     if args.workload == "serving":
         print(json.dumps({"serving_large": run_serving(n_jobs=48, seed=7, rate=2.0, N_choices=(2000, 5124, 8196),
