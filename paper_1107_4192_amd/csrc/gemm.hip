@@ -6,8 +6,8 @@
 // fragment read from LDS feeds four MFMAs. Operand tiles of 16 k-steps are
 // staged through double-buffered LDS in a fixed [k][row] layout whatever the
 // global layout (transposing loads are done on the way in), with one barrier
-// per k-tile; the next tile's global loads are in flight while the current
-// one is multiplied.
+// per k-tile. Global loads run two k-tiles ahead into two register sets, so
+// the LDS stores of the next tile go out with the current tile's MFMAs.
 //
 // Used for every dense product of the filter and smoother: X P_{t|t-1} and
 // X P X^T (eqn8), the rank-m downdate of the covariance update after eqn10,
@@ -533,18 +533,21 @@ __device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int
         for (int b = 0; b < 4; ++b) acc[a][b] = AV{0, 0, 0, 0};
 
     if (nk > 0) {
-        T ra[8], rb[8];
-        oa.fetch(ra, klo, khi);
-        ob.fetch(rb, klo, khi);
-        stash<T>(As, ra, !TA, tid);
-        stash<T>(Bs, rb, TB, tid);
+        // Two register sets: tile kt + 1 was loaded one k-tile earlier, so its LDS stores can go
+        // out with tile kt's MFMAs; tile kt + 2 is loaded meanwhile into the other set.
+        T ra0[8], rb0[8], ra1[8], rb1[8];
+        oa.fetch(ra0, klo, khi);
+        ob.fetch(rb0, klo, khi);
+        stash<T>(As, ra0, !TA, tid);
+        stash<T>(Bs, rb0, TB, tid);
+        oa.fetch(ra1, klo + BK, khi);
+        ob.fetch(rb1, klo + BK, khi);
         __syncthreads();
-        for (int kt = 0; kt < nk; ++kt) {
+        auto step = [&](int kt, T (&rn_a)[8], T (&rn_b)[8], T (&rl_a)[8], T (&rl_b)[8]) {
             const int cur = kt & 1;
-            const int k1 = klo + (kt + 1) * BK;
-            // Prefetch the next k-tile (past the end it is fully masked and never stored).
-            oa.fetch(ra, k1, khi);
-            ob.fetch(rb, k1, khi);
+            // tile kt + 2 (past the end: clamped in-bounds loads, fully masked, never read)
+            oa.fetch(rl_a, klo + (kt + 2) * BK, khi);
+            ob.fetch(rl_b, klo + (kt + 2) * BK, khi);
             const T* as = As + cur * (BK * BM);
             const T* bs = Bs + cur * (BK * BN);
 #pragma unroll
@@ -558,14 +561,23 @@ __device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b) acc[a][b] = Acc<T>::mfma(fa[a], fb[b], acc[a][b]);
+                if (kk == 0) {   // tile kt + 1 into the other buffer (last read before the previous barrier)
+                    stash<T>(As + (cur ^ 1) * (BK * BM), rn_a, !TA, tid);
+                    stash<T>(Bs + (cur ^ 1) * (BK * BN), rn_b, TB, tid);
+                    // one LDS store after each MFMA (mask 0x008: MFMA, 0x200: LDS write), so that
+                    // the stores drain while the matrix cores work instead of ahead of the barrier
+#pragma unroll
+                    for (int g = 0; g < 10; ++g) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+                    }
+                }
             }
-            // Every MFMA of this k-tile is issued before the next tile is stored: the stores wait
-            // for the prefetch loads, and kept after the MFMAs those loads get the whole k-tile's
-            // MFMA time to arrive (the compiler otherwise hoists the stores above a third of them).
-            __builtin_amdgcn_sched_barrier(0);
-            stash<T>(As + (cur ^ 1) * (BK * BM), ra, !TA, tid);
-            stash<T>(Bs + (cur ^ 1) * (BK * BN), rb, TB, tid);
             __syncthreads();
+        };
+        for (int kt = 0; kt < nk; kt += 2) {
+            step(kt, ra1, rb1, ra0, rb0);
+            if (kt + 1 < nk) step(kt + 1, ra0, rb0, ra1, rb1);
         }
     }
     epilogue<T>(P, acc, i0, j0, split, slot, tid);
