@@ -499,7 +499,22 @@ struct Operand {
     }
 };
 
-template <typename T, bool TA, bool TB>
+// 16 x 16 blocks of this wave's 64 x 64 sub-tile that hold part of C: bit 4 a + b is set unless
+// block (a, b) lies wholly below row M, right of column N, or (lower tiles only) above the diagonal.
+__device__ __forceinline__ unsigned live_blocks(const GemmDesc& P, int i0, int j0, int wm, int wn) {
+    const bool lower = P.flags & G_LOWER;
+    unsigned m = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r = i0 + wm + 16 * a, c = j0 + wn + 16 * b;
+            if (r < P.M && c < P.N && !(lower && c > r + 15)) m |= 1u << (4 * a + b);
+        }
+    return m;
+}
+
+template <typename T, bool TA, bool TB, bool EDGE = false>
 __device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int split, int slot, T* As, T* Bs) {
     using AV = typename Acc<T>::V;
     const int tid = threadIdx.x;
@@ -525,6 +540,9 @@ __device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
     const int lr = lane & 15, lk = lane >> 4;
+    // edge tiles: skip the MFMAs of blocks that hold no part of C (wave-uniform mask)
+    const unsigned live = EDGE ? live_blocks(P, i0, j0, __builtin_amdgcn_readfirstlane(wm),
+                                             __builtin_amdgcn_readfirstlane(wn)) : 0xFFFFu;
 
     AV acc[4][4];
 #pragma unroll
@@ -560,7 +578,8 @@ __device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] = Acc<T>::mfma(fa[a], fb[b], acc[a][b]);
+                    for (int b = 0; b < 4; ++b)
+                        if (!EDGE || (live >> (4 * a + b)) & 1u) acc[a][b] = Acc<T>::mfma(fa[a], fb[b], acc[a][b]);
                 if (kk == 0) {   // tile kt + 1 into the other buffer (last read before the previous barrier)
                     stash<T>(As + (cur ^ 1) * (BK * BM), rn_a, !TA, tid);
                     stash<T>(Bs + (cur ^ 1) * (BK * BN), rn_b, TB, tid);
@@ -613,10 +632,21 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmGroup G) {
     int bm, bn;
     decode_tile(P, local, bm, bn);
     const int lay = (P.flags & G_TA ? 1 : 0) | (P.flags & G_TB ? 2 : 0);
-    if ((MASK & 1) && lay == 0) fast_tile<T, false, false>(P, bm, bn, split, slot, As, Bs);
-    else if ((MASK & 2) && lay == 1) fast_tile<T, true, false>(P, bm, bn, split, slot, As, Bs);
-    else if ((MASK & 4) && lay == 2) fast_tile<T, false, true>(P, bm, bn, split, slot, As, Bs);
-    else if ((MASK & 8) && lay == 3) fast_tile<T, true, true>(P, bm, bn, split, slot, As, Bs);
+    // Tiles with at most 48 rows or columns left inside C (the 4-wide edge of N = 5124, for
+    // instance) skip the MFMAs of their empty 16 x 16 blocks, which shortens every wave of the
+    // tile; they run a separate instantiation, so interior tiles are unchanged. (Wider edges and
+    // the diagonal tiles of lower outputs would only idle some waves while the others set the pace.)
+    const bool edge = P.M - bm * BM <= 48 || P.N - bn * BN <= 48;
+#define KF_T(ta, tb)                                                                    \
+    do {                                                                                \
+        if (edge) fast_tile<T, ta, tb, true>(P, bm, bn, split, slot, As, Bs);           \
+        else fast_tile<T, ta, tb, false>(P, bm, bn, split, slot, As, Bs);               \
+    } while (0)
+    if ((MASK & 1) && lay == 0) KF_T(false, false);
+    else if ((MASK & 2) && lay == 1) KF_T(true, false);
+    else if ((MASK & 4) && lay == 2) KF_T(false, true);
+    else if ((MASK & 8) && lay == 3) KF_T(true, true);
+#undef KF_T
 }
 
 // Tile-wise reduction of a G_TILEPART range: one workgroup per tile sums the k slices in a
