@@ -98,6 +98,9 @@ struct kf_plan {
     void* tail_ws = nullptr;
     void* tail_ws64 = nullptr;              // mixed plan with a transition F: eqn13 runs in float64
     hipStream_t s2[kMaxProd] = {};
+    // filter: the m x m chain on a few compute units of their own (its small, latency-bound
+    // launches then never wait behind downdate workgroups), the downdates on the others
+    hipStream_t sc = nullptr, sdm = nullptr;
     hipEvent_t ev_start = nullptr, ev_gain[kMaxProd + 1] = {}, ev_chain[kMaxProd + 1] = {};
     // filter: L_t^{-1} formed, G_t formed, B_t refreshed (t % kBRefresh == 0), N-side of step t done,
     // C_t formed, downdate t done; slot t & 1
@@ -680,6 +683,32 @@ size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt) {
 
 namespace kfmeg {
 
+// Compute units given to the filter's m x m chain (the first ones of the device).
+constexpr int kChainCUs = 32;
+
+// Streams for the filter: the chain on the first kChainCUs compute units, the downdates on the
+// rest. Left null (the filter then uses the plan's and the side streams) if the device has too
+// few compute units or a CU-masked stream cannot be created.
+void split_filter_streams(kf_plan* p) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 4 * kChainCUs) {
+        (void)hipGetLastError();
+        return;
+    }
+    std::vector<uint32_t> mc((cus + 31) / 32, 0u), md(mc.size(), 0u);
+    for (int c = 0; c < cus; ++c) (c < kChainCUs ? mc : md)[c / 32] |= 1u << (c % 32);
+    const uint32_t n = (uint32_t)mc.size();
+    if (hipExtStreamCreateWithCUMask(&p->sc, n, mc.data()) != hipSuccess ||
+        hipExtStreamCreateWithCUMask(&p->sdm, n, md.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        for (hipStream_t* q : {&p->sc, &p->sdm})
+            if (*q) (void)hipStreamDestroy(*q);
+        p->sc = p->sdm = nullptr;
+    }
+}
+
 // kf_create with an optional arena for every device buffer of the plan (serving).
 kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const double* X, const double* Q,
                       const double* R, const double* x0, const double* P0, const kf_options* opt, void* stream,
@@ -823,6 +852,7 @@ kf_status create_plan(kf_plan** out, int64_t N, int64_t m, int64_t T_max, const 
     {
         bool ok = hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming) == hipSuccess;
         for (int q = 0; ok && q < p->nprod; ++q) ok = hipStreamCreateWithFlags(&p->s2[q], hipStreamNonBlocking) == hipSuccess;
+        if (ok && !arena) split_filter_streams(p);
         for (int k = 0; ok && k <= p->nprod; ++k)
             ok = hipEventCreateWithFlags(&p->ev_gain[k], hipEventDisableTiming) == hipSuccess &&
                  hipEventCreateWithFlags(&p->ev_chain[k], hipEventDisableTiming) == hipSuccess;
@@ -921,11 +951,18 @@ static kf_status filter_impl(kf_plan* p, int64_t B, int64_t T, const double* Y, 
         HIPCK(copy2d((int)B, (int)N, p->Xb0, false, p->ldN, p->x0, false, 0, s));   // x0 in every row
     }
     const bool direct = !p->store32 && p->stride == 1;   // store slot t is the working P
-    // Streams: the m x m chain on the plan's stream s; the N-sized work of each step (C_t, the mean,
-    // B's recursion and refreshes) on sa; the downdates on sd (= sa with one side stream). Slot
+    // Streams: the m x m chain on s (the plan's stream, or the chain's CU-masked stream); the
+    // N-sized work of each step (C_t, the mean, B's recursion and refreshes) on sa; the downdates on
+    // sd (the other CU-masked stream, else the second side stream, = sa with one side stream). Slot
     // t & 1 of L^{-1} and C is reused at step t + 2, after the streams that read it at step t.
     hipStream_t sa = p->s2[0], sd = p->nprod > 1 ? p->s2[1] : p->s2[0];
     HIPCK(hipEventRecord(p->ev_start, s));
+    const hipStream_t s0 = s;
+    if (p->sc) {   // the chain and the downdates on their CU-partitioned streams
+        s = p->sc;
+        sd = p->sdm;
+        HIPCK(hipStreamWaitEvent(s, p->ev_start, 0));
+    }
     HIPCK(hipStreamWaitEvent(sa, p->ev_start, 0));
     if (sd != sa) HIPCK(hipStreamWaitEvent(sd, p->ev_start, 0));
     const double* prev64 = p->P0;
@@ -987,8 +1024,9 @@ static kf_status filter_impl(kf_plan* p, int64_t B, int64_t T, const double* Y, 
         HIPCK(hipEventRecord(p->ev_dd[k], sd));
         prev64 = out64;
     }
-    HIPCK(hipStreamWaitEvent(s, p->ev_fa[(T - 1) & 1], 0));
-    HIPCK(hipStreamWaitEvent(s, p->ev_dd[(T - 1) & 1], 0));
+    HIPCK(hipStreamWaitEvent(s0, p->ev_fg[(T - 1) & 1], 0));
+    HIPCK(hipStreamWaitEvent(s0, p->ev_fa[(T - 1) & 1], 0));
+    HIPCK(hipStreamWaitEvent(s0, p->ev_dd[(T - 1) & 1], 0));
     return sync_and_check(p, "kf_filter");
 }
 
@@ -1771,6 +1809,8 @@ void kf_destroy(kf_plan* p) {
         for (hipEvent_t e : {p->ev_fl[k], p->ev_fg[k], p->ev_fr[k], p->ev_fa[k], p->ev_cc[k], p->ev_dd[k]})
             if (e) (void)hipEventDestroy(e);
     for (hipStream_t q : p->s2)
+        if (q) (void)hipStreamDestroy(q);
+    for (hipStream_t q : {p->sc, p->sdm})
         if (q) (void)hipStreamDestroy(q);
     for (double* b : {p->Eb, p->Wb, p->Xb0, p->Vb, p->Ub})
         if (b) (void)hipFree(b);
