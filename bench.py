@@ -38,7 +38,8 @@ Besides the contract's JSON fields the line carries:
                 N=8196, T=150 job cannot fit without checkpointing.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--T 200] [--no-cpu] [--no-mixed] [--no-serving]
-                       [--no-extra] [--no-free] [--workload paper|free|serving]
+                       [--no-extra] [--no-free] [--workload paper|tiny|free|serving|serving5] [--jobs J]
+                       [--config 1-5]
 """
 from __future__ import annotations
 
@@ -561,10 +562,22 @@ def main():
     ap.add_argument("--no-free", action="store_true", help="skip the free-orientation leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the mean-only, batched and associative-scan legs")
     ap.add_argument("--jobs", type=int, default=64, help="jobs of the 64-job stream run by --workload serving5")
-    ap.add_argument("--workload", choices=("paper", "free", "serving", "serving5"), default="paper",
+    ap.add_argument("--config", type=int, choices=(1, 2, 3, 4, 5),
+                    help="1 tiny FP64 (N=500, m=60, T=50); 2 paper scale FP64 (the default line); 3 paper scale "
+                         "FP64 and mixed only; 4 free orientation; 5 the 64-job serving stream")
+    ap.add_argument("--workload", choices=("paper", "tiny", "free", "serving", "serving5"), default="paper",
                     help="free: the free-orientation N=15372 workload only (full store and checkpointed); "
                          "serving: a larger serving run only (48 jobs up to N=8196 under a 96 GiB budget)")
     args = ap.parse_args()
+    if args.config == 1:
+        args.workload, args.T = "tiny", 50
+        args.no_free = args.no_serving = True
+    elif args.config == 3:
+        args.no_extra = args.no_free = args.no_serving = True
+    elif args.config == 4:
+        args.workload = "free"
+    elif args.config == 5:
+        args.workload = "serving5"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the multi-GPU sharding "
               "of this path is a design, not a build", file=sys.stderr)
@@ -595,7 +608,12 @@ def main():
     if args.calib_copy:
         calibration_copy()
     t0 = time.perf_counter()
-    p = synth.paper(T=args.T, N=args.N, m=args.m)
+    if args.workload == "tiny":
+        p = synth.tiny(T=args.T)
+        what = f"tiny fixed orientation: N={p.N} sources, m={p.m} sensors, T={p.T}, float64"
+    else:
+        p = synth.paper(T=args.T, N=args.N, m=args.m)
+        what = f"paper-scale fixed orientation: N={p.N} sources, m={p.m} sensors, T={p.T}, float64"
     log(f"workload N={p.N} m={p.m} T={p.T} generated in {time.perf_counter() - t0:.1f} s")
 
     r64 = run_gpu(p, kfmeg.KF_FP64, args.steps, args.warmup, profile=True, isolated=True)
@@ -619,14 +637,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded dipole lead field on a spherical shell, Gaussian-kernel Q, 3 sinusoidal patches, 5 dB)",
-        "config": {"workload": "paper-scale fixed orientation: N=5124 sources, m=306 sensors, T=200, float64",
+        "config": {"workload": what,
                    "N": p.N, "m": p.m, "T": p.T, "precision": "fp64", "store": "fp64",
                    "step": "one benchmark step = one pass of kf_filter over T time steps + kf_smooth",
                    "filter_s_per_pass": r64["t_filter"], "smoother_s_per_pass": r64["t_smooth"]},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_F64 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_F64, "traffic": measured_traffic(kflops / max(launches, 1)),
-                     "kernel": KERNEL + " (smoother N x N x N products: A_t factors and eqn13), overlapped "
-                               "with the gain streams as in the timed passes",
+                     "kernel": KERNEL + " (the smoother's eqn13 products M = A_t D and P_t + M A_t^T), "
+                               "overlapped with the gain streams as in the timed passes",
                      "launches": launches, "avg_launch_ms": kms / max(launches, 1),
                      "flops_per_launch": kflops / max(launches, 1),
                      # the same products in one extra smoother pass serialised onto one stream
