@@ -258,11 +258,17 @@ int gain_block_width(int n, int nb) {
 
 hipError_t chol_blocked_batch(int n, int nb, double* const* W, int64_t ldw, double* const* D, int64_t ldd,
                               double* const* Tb, int64_t ldt, int count, DevStatus* status, int which,
-                              const int* steps, hipStream_t s) {
-    if (count < 1 || count > kMaxBatch || nb < 1 || ldd < gain_block_width(n, nb) || ldt < n)
+                              const int* steps, hipStream_t s, const double* const* Pa, const double* Qa) {
+    if (count < 1 || count > kMaxBatch || nb < 1 || ldd < gain_block_width(n, nb) || ldt < n || (!Pa != !Qa))
         return hipErrorInvalidValue;
     const Blocks bl{n, nb};
     hipError_t e;
+    if (Pa) {   // the first block column of Pa + Qa (diagonal block and panel); the rest comes in below
+        for (int b = 0; b < count; ++b)
+            if ((e = axpby3(n, bl.hi(0), W[b], false, ldw, Pa[b], false, ldw, Qa, false, ldw, 1.0, nullptr, false,
+                            0, 0.0, s)) != hipSuccess)
+                return e;
+    }
     for (int k = 0; k < bl.count(); ++k) {
         const int r0 = bl.lo(k), r1 = bl.hi(k), nbk = r1 - r0, nr = n - r1;
         double* Wd[kMaxBatch];
@@ -290,7 +296,12 @@ hipError_t chol_blocked_batch(int n, int nb, double* const* W, int64_t ldw, doub
             g.A = Tb[b]; g.lda = ldt; g.flags = G_TA | G_LOWER;
             g.B = Tb[b]; g.ldb = ldt;
             g.alpha = -1.0; g.beta = 1.0;
-            g.Cin = W[b] + (int64_t)r1 * ldw + r1; g.ldcin = ldw;
+            if (Pa && k == 0) {   // (Pa + Qa)_{>0,>0} - L L^T
+                g.Cin = Pa[b] + (int64_t)r1 * ldw + r1; g.ldcin = ldw;
+                g.Cin2 = Qa + (int64_t)r1 * ldw + r1; g.ldcin2 = ldw; g.gamma = 1.0;
+            } else {
+                g.Cin = W[b] + (int64_t)r1 * ldw + r1; g.ldcin = ldw;
+            }
             g.C = W[b] + (int64_t)r1 * ldw + r1; g.ldc = ldw;
         }
         if ((e = gain_launch(pr, count, s)) != hipSuccess) return e;

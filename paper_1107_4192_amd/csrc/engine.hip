@@ -1113,16 +1113,14 @@ kf_status gain_batch(kf_plan* p, int set, int q, int count, const int64_t* ts, c
             HIPCK(spmm_rows(p->F, P64[b], ld, 1.0, nullptr, 0, 0.0, nullptr, 0, 0.0, p->Ab[set][b], false, ld, s));
             rhs[b] = p->Ab[set][b];
         } else {
-            // W = P_t + Q  (= P_{t+1|t}, eqn7)
-            HIPCK(axpby3(N, N, Wq[b], false, ld, P64[b], false, ld, p->Q, false, ld, 1.0, nullptr, false, 0, 0.0,
-                         s));
-            rhs[b] = P64[b];
+            rhs[b] = P64[b];      // W = P_t + Q (= P_{t+1|t}, eqn7) is formed inside the factorisation
         }
         Db[b] = p->Dg[q][b];
         Tb[b] = p->Dg[q][b] + (size_t)N * p->gld;
         steps[b] = (int)ts[b] + 1;
     }
-    HIPCK(chol_blocked_batch(N, p->gnb, Wq, ld, Db, p->gld, Tb, ld, count, p->dstatus, W_PPRED, steps, s));
+    HIPCK(chol_blocked_batch(N, p->gnb, Wq, ld, Db, p->gld, Tb, ld, count, p->dstatus, W_PPRED, steps, s,
+                             p->hasF ? nullptr : P64, p->hasF ? nullptr : p->Q));
     HIPCK(trsm_lower_batch(N, p->gnb, Wq, ld, Db, p->gld, Tb, ld, rhs, ld, Yq, ld, count, s));
     HIPCK(trsm_upper_t_batch(N, p->gnb, Wq, ld, Db, p->gld, Tb, ld, Yq, ld, p->Ab[set], ld, count, s));
     TransposeInPlace tr;
@@ -1158,12 +1156,7 @@ kf_status chain_step(kf_plan* p, int set, int b, int64_t t, const void* Pt, cons
     // float32 accumulation loses the stated accuracy: eqn13 then runs in float64 in both precisions.
     if (mixed(p) && !p->hasF) {
         // D = P_{t+1|T} - P_t - Q in float32; M = A D; P_{t|T} = P_t + M A^T   (eqn13)
-        if (p->hasF) {                      // D = P_{t+1|T} - F (P_t F^T) - Q
-            HIPCK(dense_sparse_t(p->F, Pt64, ld, p->Fg, ld, s));
-            HIPCK(spmm_rows(p->F, p->Fg, ld, -1.0, Ps_next, ld, 1.0, p->Q, ld, -1.0, p->D32, true, ld, s));
-        } else {
-            HIPCK(axpby3(N, N, p->D32, true, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
-        }
+        HIPCK(axpby3(N, N, p->D32, true, ld, Ps_next, false, ld, Pt64, false, ld, -1.0, p->Q, false, ld, -1.0, s));
         GemmProblem g;
         g.M = N; g.N = N; g.K = N;
         g.A = p->A32[set][b]; g.lda = ld; g.B = p->D32; g.ldb = ld; g.flags = G_TB;   // D symmetric

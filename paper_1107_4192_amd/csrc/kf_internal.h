@@ -117,9 +117,13 @@ int gain_block_width(int n, int nb);
 // scratch) and D (n x nb, ld ldd >= nb) holds the inverse of diagonal block k in rows
 // [k nb, k nb + nb_k), lower triangular with explicit zeros (ldd >= gain_block_width(n, nb)).
 // Tb: gain_block_width(n, nb) x n scratch, ld ldt >= n.
+// With Pa (count matrices) and Qa (one, both ld ldw) the matrices factored are Pa[b] + Qa and W
+// holds nothing on entry: the sum is formed only for the first block column, and the first
+// trailing update reads Pa and Qa in its epilogue (one N x N pass per matrix less).
 hipError_t chol_blocked_batch(int n, int nb, double* const* W, int64_t ldw, double* const* D, int64_t ldd,
                               double* const* Tb, int64_t ldt, int count, DevStatus* status, int which,
-                              const int* steps, hipStream_t s);
+                              const int* steps, hipStream_t s, const double* const* Pa = nullptr,
+                              const double* Qa = nullptr);
 // Y = L^{-1} B (B, Y: n x n) with L, D from chol_blocked_batch; block row k is
 // Y_k = Li_kk (B_k - L_{k,<k} Y_{<k}). Y must not alias B, W or D; Tb is scratch.
 hipError_t trsm_lower_batch(int n, int nb, const double* const* W, int64_t ldw, const double* const* D, int64_t ldd,
