@@ -1,11 +1,11 @@
 // Blocked Cholesky factorisation fused with the inverse of the factor (float64),
 // for a batch of independent matrices.
 //
-// The filter needs S^{-1} in eqn8/eqn9 and the smoother needs P_{t+1|t}^{-1}
-// in eqn11. Both are applied through the lower Cholesky factor L and its
-// inverse Li = L^{-1}: S^{-1} B = Li^T (Li B), and the smoother gain
-// A_t = P_{t|t} P_{t+1|t}^{-1} = (Li P_{t|t})^T Li. Li is obtained by solving
-// L Z = I in the same right-looking sweep as the factorisation.
+// The filter needs S^{-1} in eqn8/eqn9, applied through the lower Cholesky
+// factor L and its inverse Li = L^{-1}: S^{-1} B = Li^T (Li B). Li is obtained
+// by solving L Z = I in the same right-looking sweep as the factorisation. The
+// smoother's P_{t+1|t}^{-1} in eqn11 uses the same sweep only for the diagonal
+// blocks of an outer-blocked factorisation (second half of this file).
 //
 // Two-level blocking keeps the O(n^3) work in large MFMA products with a long
 // K dimension:
