@@ -686,17 +686,32 @@ bool fast_ok(const void* p, int64_t ld, int contig) {
     return p && aligned16(p) && ld % 8 == 0 && ld >= ((contig + 7) & ~7);
 }
 
+// Only the layout masks a variant is used with are compiled for it (the eqn13 products are all
+// NT; the gain's launches NN, TN or NT); any other mask runs the unnamed variant's kernel, which
+// computes the same thing. This keeps the library's build time and size in check.
 template <typename T, int V>
 hipError_t launch_fast(const GemmGroup& G, int mask, hipStream_t s) {
     const dim3 grid(G.total_tiles), block(NT);
 #define KF_L(m) hipLaunchKernelGGL((gemm_kernel<T, V, m>), grid, block, 0, s, G)
-    switch (mask) {
-        case 1: KF_L(1); break;
-        case 2: KF_L(2); break;
-        case 4: KF_L(4); break;
-        case 8: KF_L(8); break;
-        case 5: KF_L(5); break;
-        default: KF_L(15); break;
+    if constexpr (V == 0) {
+        switch (mask) {
+            case 1: KF_L(1); break;
+            case 2: KF_L(2); break;
+            case 4: KF_L(4); break;
+            case 8: KF_L(8); break;
+            case 5: KF_L(5); break;
+            default: KF_L(15); break;
+        }
+    } else if constexpr (V == 4) {
+        switch (mask) {
+            case 1: KF_L(1); break;
+            case 2: KF_L(2); break;
+            case 4: KF_L(4); break;
+            default: return launch_fast<T, 0>(G, mask, s);
+        }
+    } else {
+        if (mask != 4) return launch_fast<T, 0>(G, mask, s);
+        KF_L(4);
     }
 #undef KF_L
     return hipGetLastError();
