@@ -17,7 +17,12 @@
  *    buffers must stay valid for the duration of the call.
  *  - Work is enqueued on the plan's stream (a hipStream_t passed as void*,
  *    NULL = the null stream) and every call synchronises that stream before it
- *    returns, so the returned status is final.
+ *    returns, so the returned status is final. A plan also owns streams of its
+ *    own (the smoother's gain batches and the filter's N-sized work run on side
+ *    streams; on a device with at least 128 compute units, the filter's m x m
+ *    chain and its covariance downdates run on two streams restricted to
+ *    disjoint sets of compute units); every call orders them after the plan's
+ *    stream at its start and joins them back into it before it returns.
  *  - Argument errors are reported before any launch. Nothing throws or
  *    aborts across this boundary; kf_last_error() gives a message.
  *  - A plan is used by one host thread at a time; distinct plans may run
