@@ -562,6 +562,7 @@ def main():
     ap.add_argument("--no-free", action="store_true", help="skip the free-orientation leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the mean-only, batched and associative-scan legs")
     ap.add_argument("--jobs", type=int, default=64, help="jobs of the 64-job stream run by --workload serving5")
+    ap.add_argument("--first", type=int, default=0, help="first job of the 64-job stream run by --workload serving5")
     ap.add_argument("--config", type=int, choices=(1, 2, 3, 4, 5),
                     help="1 tiny FP64 (N=500, m=60, T=50); 2 paper scale FP64 (the default line); 3 paper scale "
                          "FP64 and mixed only; 4 free orientation; 5 the 64-job serving stream")
@@ -594,9 +595,11 @@ def main():
         print(json.dumps({"free_orientation": run_free(T=min(args.T, 100))}), flush=True)
         return
     if args.workload == "serving5":
-        # the 64-job stream of mixed N (2000 to 15372), m and T (50 to 400) at 4 arrivals/s; the
-        # first --jobs of it, in arrival order
-        plan = synth.serving_jobs(seed=5, n_jobs=64)[:args.jobs]
+        # the 64-job stream of mixed N (2000 to 15372), m and T (50 to 400) at 4 arrivals/s; --jobs
+        # of it from job --first on, in arrival order
+        plan = synth.serving_jobs(seed=5, n_jobs=64)[args.first:args.first + args.jobs]
+        t_first = plan[0]["arrival_s"]
+        plan = [dict(j, arrival_s=j["arrival_s"] - t_first) for j in plan]   # arrivals from 0
         print(json.dumps({"serving_stream64": run_serving(plan=plan, max_active=4, estimate_baseline=True)}),
               flush=True)
         return
