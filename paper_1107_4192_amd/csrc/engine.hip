@@ -953,14 +953,16 @@ static kf_status filter_impl(kf_plan* p, int64_t B, int64_t T, const double* Y, 
     const bool direct = !p->store32 && p->stride == 1;   // store slot t is the working P
     // Streams: the m x m chain on s (the plan's stream, or the chain's CU-masked stream); the
     // N-sized work of each step (C_t, the mean, B's recursion and refreshes) on sa; the downdates on
-    // sd (the other CU-masked stream, else the second side stream, = sa with one side stream). Slot
-    // t & 1 of L^{-1} and C is reused at step t + 2, after the streams that read it at step t.
+    // sd. With the CU split both sa and sd are the other CU-masked stream; otherwise sa is the first
+    // side stream and sd the second (= sa with one side stream). Slot t & 1 of L^{-1} and C is
+    // reused at step t + 2, after the streams that read it at step t.
     hipStream_t sa = p->s2[0], sd = p->nprod > 1 ? p->s2[1] : p->s2[0];
     HIPCK(hipEventRecord(p->ev_start, s));
     const hipStream_t s0 = s;
-    if (p->sc) {   // the chain and the downdates on their CU-partitioned streams
+    if (p->sc) {   // the chain on its CU-partitioned stream, the N-sized work and downdates on the other
         s = p->sc;
         sd = p->sdm;
+        sa = p->sdm;
         HIPCK(hipStreamWaitEvent(s, p->ev_start, 0));
     }
     HIPCK(hipStreamWaitEvent(sa, p->ev_start, 0));
