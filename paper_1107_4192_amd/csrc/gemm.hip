@@ -6,8 +6,11 @@
 // fragment read from LDS feeds four MFMAs. Operand tiles of 16 k-steps are
 // staged through double-buffered LDS in a fixed [k][row] layout whatever the
 // global layout (transposing loads are done on the way in), with one barrier
-// per k-tile. Global loads run two k-tiles ahead into two register sets, so
-// the LDS stores of the next tile go out with the current tile's MFMAs.
+// per k-tile. Float64 tiles go from global memory straight into LDS
+// (global_load_lds_dwordx4, one k-tile ahead), with no staging registers and no
+// LDS store instructions; a partial last k-tile, which must read zeros past K,
+// takes the register path. Float32 tiles load two k-tiles ahead into two
+// register sets, and their LDS stores go out with the current tile's MFMAs.
 //
 // Used for every dense product of the filter and smoother: X P_{t|t-1} and
 // X P X^T (eqn8), the rank-m downdate of the covariance update after eqn10,
@@ -602,6 +605,154 @@ __device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int
     epilogue<T>(P, acc, i0, j0, split, slot, tid);
 }
 
+// ---- float64 tiles loaded straight into LDS (global_load_lds_dwordx4: each lane's 16 bytes land
+// at the instruction's LDS base + 16 x lane). Each wave issues 4 such loads per operand and k-tile.
+// A row-contiguous operand is staged as [k pair][row][2] (a lane loads two consecutive k of one
+// row), a k-major one as [k][column]. Rows and columns past the matrix read clamped, in-bounds
+// addresses (their products only reach outputs outside C); k never runs past the tile's range
+// here, since a partial last k-tile takes the register path, which zeroes k >= khi.
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <bool RC>
+struct DmaOp {
+    const double* p0;   // row-contiguous: row i0 + lane; k-major: matrix base + this lane's 2 columns
+    const double* p1;   // row-contiguous: row i0 + 64 + lane
+    int64_t ld;
+    __device__ __forceinline__ void init(const double* M, int64_t ld_, int rows, int t0, int lane) {
+        ld = ld_;
+        if constexpr (RC) {
+            p0 = M + (int64_t)min(t0 + lane, rows - 1) * ld;
+            p1 = M + (int64_t)min(t0 + 64 + lane, rows - 1) * ld;
+        } else {
+            p0 = M + min(t0 + 2 * lane, max(round8(rows) - 2, 0));
+            p1 = p0;
+        }
+    }
+    // tile k0..k0+15 into S: row-contiguous as [k pair][row][2], k-major as [k][col]
+    __device__ __forceinline__ void issue(int k0, double* S, int wave) const {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if constexpr (RC) {
+                const int c = wave * 2 + (i >> 1), h = i & 1;
+                const double* src = (h ? p1 : p0) + k0 + 2 * c;
+                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(S + (c * 128 + h * 64) * 2), 16, 0, 0);
+            } else {
+                const int kr = wave * 4 + i;
+                const double* src = p0 + (int64_t)(k0 + kr) * ld;
+                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(S + kr * 128), 16, 0, 0);
+            }
+        }
+    }
+};
+
+// register-path store of a row-contiguous operand in the [k pair][row][2] layout
+__device__ __forceinline__ void stash_pairs(double* S, const double (&r)[8], int tid) {
+    const int rr = tid & 127, p0 = (tid >> 7) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) reinterpret_cast<d2*>(S)[(p0 + q) * 128 + rr] = d2{r[2 * q], r[2 * q + 1]};
+}
+
+template <bool TA, bool TB, bool EDGE>
+__device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn, int split, int slot, double* As0,
+                                              double* As1, double* Bs0, double* Bs1) {
+    using AV = Acc<double>::V;
+    const int tid = threadIdx.x;
+    const int i0 = bm * BM, j0 = bn * BN;
+    int klo = 0, khi = P.K;
+    if (P.flags & G_ALOWER) khi = min(khi, i0 + BM);
+    if (P.flags & G_BUPPER) khi = min(khi, j0 + BN);
+    if (P.flags & G_BLOWER) klo = max(klo, j0);
+    if (P.flags & G_AUPPER) klo = max(klo, i0);
+    if (P.ksplit > 1) {
+        const int span = max(khi - klo, 0);
+        const int chunk = ((span + P.ksplit - 1) / P.ksplit + BK - 1) / BK * BK;
+        klo = klo + split * chunk;
+        khi = min(khi, klo + chunk);
+    }
+    const int nk = khi > klo ? (khi - klo + BK - 1) / BK : 0;
+    const bool tail = ((khi - klo) & (BK - 1)) != 0;     // the last k-tile is partial
+    constexpr bool RA = !TA, RB = TB;
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const unsigned live = EDGE ? live_blocks(P, i0, j0, __builtin_amdgcn_readfirstlane(wm),
+                                             __builtin_amdgcn_readfirstlane(wn)) : 0xFFFFu;
+    DmaOp<RA> da;
+    DmaOp<RB> db;
+    da.init(static_cast<const double*>(P.A), P.lda, P.M, i0, lane);
+    db.init(static_cast<const double*>(P.B), P.ldb, P.N, j0, lane);
+    Operand<double, RA> oa;
+    Operand<double, RB> ob;
+    oa.init(static_cast<const double*>(P.A), P.lda, P.M, P.K, i0, tid);
+    ob.init(static_cast<const double*>(P.B), P.ldb, P.N, P.K, j0, tid);
+
+    AV acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = AV{0, 0, 0, 0};
+
+    auto put = [&](double* Sa, double* Sb, const double (&ra)[8], const double (&rb)[8]) {
+        if constexpr (RA) stash_pairs(Sa, ra, tid); else stash<double>(Sa, ra, false, tid);
+        if constexpr (RB) stash_pairs(Sb, rb, tid); else stash<double>(Sb, rb, false, tid);
+    };
+    auto rd = [&](const double* S, bool rc, int k, int row) -> double {
+        return rc ? S[((k >> 1) * 128 + row) * 2 + (k & 1)] : S[k * 128 + row];
+    };
+    auto tile = [&](const double* as, const double* bs) {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double fa[4], fb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) fa[a] = rd(as, RA, kk + lk, wm + a * 16 + lr);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) fb[b] = rd(bs, RB, kk + lk, wn + b * 16 + lr);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (!EDGE || (live >> (4 * a + b)) & 1u) acc[a][b] = Acc<double>::mfma(fa[a], fb[b], acc[a][b]);
+        }
+    };
+    if (nk > 0) {
+        if (nk == 1 && tail) {
+            double ra[8], rb[8];
+            oa.fetch(ra, klo, khi);
+            ob.fetch(rb, klo, khi);
+            put(As0, Bs0, ra, rb);
+        } else {
+            da.issue(klo, As0, wv);
+            db.issue(klo, Bs0, wv);
+        }
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = kt + h;
+                if (k >= nk) break;
+                double* nA = h ? As0 : As1;
+                double* nB = h ? Bs0 : Bs1;
+                const bool next = k + 1 < nk, next_reg = next && k + 1 == nk - 1 && tail;
+                double ra[8], rb[8];
+                if (next && !next_reg) {
+                    da.issue(klo + (k + 1) * BK, nA, wv);
+                    db.issue(klo + (k + 1) * BK, nB, wv);
+                }
+                if (next_reg) {
+                    oa.fetch(ra, klo + (k + 1) * BK, khi);
+                    ob.fetch(rb, klo + (k + 1) * BK, khi);
+                }
+                tile(h ? As1 : As0, h ? Bs1 : Bs0);
+                if (next_reg) put(nA, nB, ra, rb);
+                __syncthreads();
+            }
+        }
+    }
+    epilogue<double>(P, acc, i0, j0, split, slot, tid);
+}
+
 // V selects a separately named instantiation: 1 for the smoother's N x N x N
 // products of the float64 path, 2 for those of the mixed path, 3 for the float64
 // products of a smoother pass serialised onto one stream for measurement, 4 for the
@@ -612,6 +763,7 @@ template <typename T, int V, int MASK>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmGroup G) {
     __shared__ T As[2 * BK * BM];
     __shared__ T Bs[2 * BK * BN];
+    __shared__ double Ad0[BK * BM], Ad1[BK * BM], Bd0[BK * BN], Bd1[BK * BN];
     int q = 0;
 #pragma unroll
     for (int u = 1; u < kMaxGroup; ++u)
@@ -639,8 +791,13 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmGroup G) {
     const bool edge = P.M - bm * BM <= 48 || P.N - bn * BN <= 48;
 #define KF_T(ta, tb)                                                                    \
     do {                                                                                \
-        if (edge) fast_tile<T, ta, tb, true>(P, bm, bn, split, slot, As, Bs);           \
-        else fast_tile<T, ta, tb, false>(P, bm, bn, split, slot, As, Bs);               \
+        if constexpr (sizeof(T) == 8) {                                                 \
+            if (edge) fast_tile_dma<ta, tb, true>(P, bm, bn, split, slot, Ad0, Ad1, Bd0, Bd1); \
+            else fast_tile_dma<ta, tb, false>(P, bm, bn, split, slot, Ad0, Ad1, Bd0, Bd1);     \
+        } else {                                                                        \
+            if (edge) fast_tile<T, ta, tb, true>(P, bm, bn, split, slot, As, Bs);       \
+            else fast_tile<T, ta, tb, false>(P, bm, bn, split, slot, As, Bs);           \
+        }                                                                               \
     } while (0)
     if ((MASK & 1) && lay == 0) KF_T(false, false);
     else if ((MASK & 2) && lay == 1) KF_T(true, false);
