@@ -6,11 +6,10 @@
 // fragment read from LDS feeds four MFMAs. Operand tiles of 16 k-steps are
 // staged through double-buffered LDS in a fixed [k][row] layout whatever the
 // global layout (transposing loads are done on the way in), with one barrier
-// per k-tile. Float64 tiles go from global memory straight into LDS
+// per k-tile. Tiles go from global memory straight into LDS
 // (global_load_lds_dwordx4, one k-tile ahead), with no staging registers and no
 // LDS store instructions; a partial last k-tile, which must read zeros past K,
-// takes the register path. Float32 tiles load two k-tiles ahead into two
-// register sets, and their LDS stores go out with the current tile's MFMAs.
+// takes the register path.
 //
 // Used for every dense product of the filter and smoother: X P_{t|t-1} and
 // X P X^T (eqn8), the rank-m downdate of the covariance update after eqn10,
@@ -421,13 +420,13 @@ __global__ void gemm_reduce_kernel(GemmDesc P) {
 
 
 // ------------------------------------------------------------------ fast path
-// Branch-free main loop for operands whose leading dimensions are multiples of 8
-// elements with 16-byte aligned bases (all plan-owned buffers). Out-of-range rows
-// and k-steps are read from clamped, in-bounds addresses and replaced by zero with
-// a select, so the loop has no divergent control flow and the accumulators stay in
-// the accumulation registers. Layouts are compile-time (bit 0: A transposed,
-// bit 1: B transposed); a launch can carry problems of two layouts (L0 for the
-// first problem, L1 for the rest).
+// For operands whose leading dimensions are multiples of 8 elements with 16-byte
+// aligned bases (all plan-owned buffers). Out-of-range rows read clamped, in-bounds
+// addresses; the register path of a partial last k-tile also zeroes them and k past
+// the tile's range with selects, so the loop has no divergent control flow and the
+// accumulators stay in the accumulation registers. Layouts are compile-time (bit 0:
+// A transposed, bit 1: B transposed); the MASK of a kernel names the layouts it holds,
+// and each problem of a group picks its own.
 
 __device__ __forceinline__ int round8(int v) { return (v + 7) & ~7; }
 
@@ -517,145 +516,76 @@ __device__ __forceinline__ unsigned live_blocks(const GemmDesc& P, int i0, int j
     return m;
 }
 
-template <typename T, bool TA, bool TB, bool EDGE = false>
-__device__ __forceinline__ void fast_tile(const GemmDesc& P, int bm, int bn, int split, int slot, T* As, T* Bs) {
-    using AV = typename Acc<T>::V;
-    const int tid = threadIdx.x;
-    const int i0 = bm * BM, j0 = bn * BN;
-    int klo = 0, khi = P.K;
-    if (P.flags & G_ALOWER) khi = min(khi, i0 + BM);
-    if (P.flags & G_BUPPER) khi = min(khi, j0 + BN);
-    if (P.flags & G_BLOWER) klo = max(klo, j0);
-    if (P.flags & G_AUPPER) klo = max(klo, i0);
-    if (P.ksplit > 1) {
-        const int span = max(khi - klo, 0);
-        const int chunk = ((span + P.ksplit - 1) / P.ksplit + BK - 1) / BK * BK;
-        klo = klo + split * chunk;
-        khi = min(khi, klo + chunk);
-    }
-    const int nk = khi > klo ? (khi - klo + BK - 1) / BK : 0;
-
-    Operand<T, !TA> oa;
-    Operand<T, TB> ob;
-    oa.init(static_cast<const T*>(P.A), P.lda, P.M, P.K, i0, tid);
-    ob.init(static_cast<const T*>(P.B), P.ldb, P.N, P.K, j0, tid);
-
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-    const int lr = lane & 15, lk = lane >> 4;
-    // edge tiles: skip the MFMAs of blocks that hold no part of C (wave-uniform mask)
-    const unsigned live = EDGE ? live_blocks(P, i0, j0, __builtin_amdgcn_readfirstlane(wm),
-                                             __builtin_amdgcn_readfirstlane(wn)) : 0xFFFFu;
-
-    AV acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = AV{0, 0, 0, 0};
-
-    if (nk > 0) {
-        // Two register sets: tile kt + 1 was loaded one k-tile earlier, so its LDS stores can go
-        // out with tile kt's MFMAs; tile kt + 2 is loaded meanwhile into the other set.
-        T ra0[8], rb0[8], ra1[8], rb1[8];
-        oa.fetch(ra0, klo, khi);
-        ob.fetch(rb0, klo, khi);
-        stash<T>(As, ra0, !TA, tid);
-        stash<T>(Bs, rb0, TB, tid);
-        oa.fetch(ra1, klo + BK, khi);
-        ob.fetch(rb1, klo + BK, khi);
-        __syncthreads();
-        auto step = [&](int kt, T (&rn_a)[8], T (&rn_b)[8], T (&rl_a)[8], T (&rl_b)[8]) {
-            const int cur = kt & 1;
-            // tile kt + 2 (past the end: clamped in-bounds loads, fully masked, never read)
-            oa.fetch(rl_a, klo + (kt + 2) * BK, khi);
-            ob.fetch(rl_b, klo + (kt + 2) * BK, khi);
-            const T* as = As + cur * (BK * BM);
-            const T* bs = Bs + cur * (BK * BN);
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
-                T fa[4], fb[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) fa[a] = as[(kk + lk) * BM + wm + a * 16 + lr];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) fb[b] = bs[(kk + lk) * BN + wn + b * 16 + lr];
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        if (!EDGE || (live >> (4 * a + b)) & 1u) acc[a][b] = Acc<T>::mfma(fa[a], fb[b], acc[a][b]);
-                if (kk == 0) {   // tile kt + 1 into the other buffer (last read before the previous barrier)
-                    stash<T>(As + (cur ^ 1) * (BK * BM), rn_a, !TA, tid);
-                    stash<T>(Bs + (cur ^ 1) * (BK * BN), rn_b, TB, tid);
-                    // one LDS store after each MFMA (mask 0x008: MFMA, 0x200: LDS write), so that
-                    // the stores drain while the matrix cores work instead of ahead of the barrier
-#pragma unroll
-                    for (int g = 0; g < 10; ++g) {
-                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-                    }
-                }
-            }
-            __syncthreads();
-        };
-        for (int kt = 0; kt < nk; kt += 2) {
-            step(kt, ra1, rb1, ra0, rb0);
-            if (kt + 1 < nk) step(kt + 1, ra0, rb0, ra1, rb1);
-        }
-    }
-    epilogue<T>(P, acc, i0, j0, split, slot, tid);
-}
-
-// ---- float64 tiles loaded straight into LDS (global_load_lds_dwordx4: each lane's 16 bytes land
-// at the instruction's LDS base + 16 x lane). Each wave issues 4 such loads per operand and k-tile.
-// A row-contiguous operand is staged as [k pair][row][2] (a lane loads two consecutive k of one
-// row), a k-major one as [k][column]. Rows and columns past the matrix read clamped, in-bounds
+// ---- tiles loaded straight into LDS (global_load_lds_dwordx4: each lane's 16 bytes land at the
+// instruction's LDS base + 16 x lane). Each wave issues 4 (float64) or 2 (float32) such loads per
+// operand and k-tile. A row-contiguous operand is staged as [k group][row][E] (a lane loads E
+// consecutive k of one row), a k-major one as [k][column]. Rows and columns past the matrix read clamped, in-bounds
 // addresses (their products only reach outputs outside C); k never runs past the tile's range
 // here, since a partial last k-tile takes the register path, which zeroes k >= khi.
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <bool RC>
+// E = elements per 16-byte chunk (2 float64 or 4 float32); a row-contiguous operand is staged as
+// [k group of E][row][E], a k-major one as [k][column].
+template <typename T, bool RC>
 struct DmaOp {
-    const double* p0;   // row-contiguous: row i0 + lane; k-major: matrix base + this lane's 2 columns
-    const double* p1;   // row-contiguous: row i0 + 64 + lane
+    static constexpr int E = 16 / sizeof(T);
+    const T* p0;   // row-contiguous: row i0 + lane; k-major: matrix base + this lane's E columns
+    const T* p1;   // row-contiguous: row i0 + 64 + lane
     int64_t ld;
-    __device__ __forceinline__ void init(const double* M, int64_t ld_, int rows, int t0, int lane) {
+    __device__ __forceinline__ void init(const T* M, int64_t ld_, int rows, int t0, int lane) {
         ld = ld_;
         if constexpr (RC) {
             p0 = M + (int64_t)min(t0 + lane, rows - 1) * ld;
             p1 = M + (int64_t)min(t0 + 64 + lane, rows - 1) * ld;
-        } else {
-            p0 = M + min(t0 + 2 * lane, max(round8(rows) - 2, 0));
+        } else {   // float64: 64 lanes x 2 columns per k-row; float32: 32 lanes x 4 columns, two k-rows
+            const int col = sizeof(T) == 8 ? 2 * lane : 4 * (lane & 31);
+            p0 = M + min(t0 + col, max(round8(rows) - E, 0));
             p1 = p0;
         }
     }
-    // tile k0..k0+15 into S: row-contiguous as [k pair][row][2], k-major as [k][col]
-    __device__ __forceinline__ void issue(int k0, double* S, int wave) const {
+    // tile k0..k0+15 into S
+    __device__ __forceinline__ void issue(int k0, T* S, int wave, int lane) const {
+        constexpr int NI = sizeof(T) == 8 ? 4 : 2;   // loads per wave and operand
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < NI; ++i) {
             if constexpr (RC) {
-                const int c = wave * 2 + (i >> 1), h = i & 1;
-                const double* src = (h ? p1 : p0) + k0 + 2 * c;
-                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(S + (c * 128 + h * 64) * 2), 16, 0, 0);
-            } else {
+                const int c = sizeof(T) == 8 ? wave * 2 + (i >> 1) : wave, h = i & 1;
+                const T* src = (h ? p1 : p0) + k0 + E * c;
+                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(S + (c * 128 + h * 64) * E), 16, 0, 0);
+            } else if constexpr (sizeof(T) == 8) {
                 const int kr = wave * 4 + i;
-                const double* src = p0 + (int64_t)(k0 + kr) * ld;
+                const T* src = p0 + (int64_t)(k0 + kr) * ld;
+                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(S + kr * 128), 16, 0, 0);
+            } else {
+                const int kr = (wave * 2 + i) * 2;          // k-rows kr (lanes 0-31) and kr + 1 (32-63)
+                const T* src = p0 + (int64_t)(k0 + kr + (lane >> 5)) * ld;
                 __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(S + kr * 128), 16, 0, 0);
             }
         }
     }
 };
 
-// register-path store of a row-contiguous operand in the [k pair][row][2] layout
-__device__ __forceinline__ void stash_pairs(double* S, const double (&r)[8], int tid) {
-    const int rr = tid & 127, p0 = (tid >> 7) * 4;
+// register-path store of a row-contiguous operand in the [k group][row][E] layout
+template <typename T>
+__device__ __forceinline__ void stash_groups(T* S, const T (&r)[8], int tid) {
+    const int rr = tid & 127;
+    if constexpr (sizeof(T) == 8) {
+        const int p0 = (tid >> 7) * 4;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) reinterpret_cast<d2*>(S)[(p0 + q) * 128 + rr] = d2{r[2 * q], r[2 * q + 1]};
+        for (int q = 0; q < 4; ++q) reinterpret_cast<d2*>(S)[(p0 + q) * 128 + rr] = d2{r[2 * q], r[2 * q + 1]};
+    } else {
+        const int p0 = (tid >> 7) * 2;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            reinterpret_cast<f4*>(S)[(p0 + q) * 128 + rr] = f4{r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]};
+    }
 }
 
-template <bool TA, bool TB, bool EDGE>
-__device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn, int split, int slot, double* As0,
-                                              double* As1, double* Bs0, double* Bs1) {
-    using AV = Acc<double>::V;
+template <typename T, bool TA, bool TB, bool EDGE>
+__device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn, int split, int slot, T* As0,
+                                              T* As1, T* Bs0, T* Bs1) {
+    using AV = typename Acc<T>::V;
+    constexpr int E = 16 / sizeof(T);
     const int tid = threadIdx.x;
     const int i0 = bm * BM, j0 = bn * BN;
     int klo = 0, khi = P.K;
@@ -679,14 +609,14 @@ __device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn,
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const unsigned live = EDGE ? live_blocks(P, i0, j0, __builtin_amdgcn_readfirstlane(wm),
                                              __builtin_amdgcn_readfirstlane(wn)) : 0xFFFFu;
-    DmaOp<RA> da;
-    DmaOp<RB> db;
-    da.init(static_cast<const double*>(P.A), P.lda, P.M, i0, lane);
-    db.init(static_cast<const double*>(P.B), P.ldb, P.N, j0, lane);
-    Operand<double, RA> oa;
-    Operand<double, RB> ob;
-    oa.init(static_cast<const double*>(P.A), P.lda, P.M, P.K, i0, tid);
-    ob.init(static_cast<const double*>(P.B), P.ldb, P.N, P.K, j0, tid);
+    DmaOp<T, RA> da;
+    DmaOp<T, RB> db;
+    da.init(static_cast<const T*>(P.A), P.lda, P.M, i0, lane);
+    db.init(static_cast<const T*>(P.B), P.ldb, P.N, j0, lane);
+    Operand<T, RA> oa;
+    Operand<T, RB> ob;
+    oa.init(static_cast<const T*>(P.A), P.lda, P.M, P.K, i0, tid);
+    ob.init(static_cast<const T*>(P.B), P.ldb, P.N, P.K, j0, tid);
 
     AV acc[4][4];
 #pragma unroll
@@ -694,17 +624,17 @@ __device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn,
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = AV{0, 0, 0, 0};
 
-    auto put = [&](double* Sa, double* Sb, const double (&ra)[8], const double (&rb)[8]) {
-        if constexpr (RA) stash_pairs(Sa, ra, tid); else stash<double>(Sa, ra, false, tid);
-        if constexpr (RB) stash_pairs(Sb, rb, tid); else stash<double>(Sb, rb, false, tid);
+    auto put = [&](T* Sa, T* Sb, const T (&ra)[8], const T (&rb)[8]) {
+        if constexpr (RA) stash_groups<T>(Sa, ra, tid); else stash<T>(Sa, ra, false, tid);
+        if constexpr (RB) stash_groups<T>(Sb, rb, tid); else stash<T>(Sb, rb, false, tid);
     };
-    auto rd = [&](const double* S, bool rc, int k, int row) -> double {
-        return rc ? S[((k >> 1) * 128 + row) * 2 + (k & 1)] : S[k * 128 + row];
+    auto rd = [&](const T* S, bool rc, int k, int row) -> T {
+        return rc ? S[((k / E) * 128 + row) * E + (k % E)] : S[k * 128 + row];
     };
-    auto tile = [&](const double* as, const double* bs) {
+    auto tile = [&](const T* as, const T* bs) {
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            double fa[4], fb[4];
+            T fa[4], fb[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) fa[a] = rd(as, RA, kk + lk, wm + a * 16 + lr);
 #pragma unroll
@@ -713,18 +643,18 @@ __device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn,
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    if (!EDGE || (live >> (4 * a + b)) & 1u) acc[a][b] = Acc<double>::mfma(fa[a], fb[b], acc[a][b]);
+                    if (!EDGE || (live >> (4 * a + b)) & 1u) acc[a][b] = Acc<T>::mfma(fa[a], fb[b], acc[a][b]);
         }
     };
     if (nk > 0) {
         if (nk == 1 && tail) {
-            double ra[8], rb[8];
+            T ra[8], rb[8];
             oa.fetch(ra, klo, khi);
             ob.fetch(rb, klo, khi);
             put(As0, Bs0, ra, rb);
         } else {
-            da.issue(klo, As0, wv);
-            db.issue(klo, Bs0, wv);
+            da.issue(klo, As0, wv, lane);
+            db.issue(klo, Bs0, wv, lane);
         }
         __syncthreads();
         for (int kt = 0; kt < nk; kt += 2) {
@@ -732,13 +662,13 @@ __device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn,
             for (int h = 0; h < 2; ++h) {
                 const int k = kt + h;
                 if (k >= nk) break;
-                double* nA = h ? As0 : As1;
-                double* nB = h ? Bs0 : Bs1;
+                T* nA = h ? As0 : As1;
+                T* nB = h ? Bs0 : Bs1;
                 const bool next = k + 1 < nk, next_reg = next && k + 1 == nk - 1 && tail;
-                double ra[8], rb[8];
+                T ra[8], rb[8];
                 if (next && !next_reg) {
-                    da.issue(klo + (k + 1) * BK, nA, wv);
-                    db.issue(klo + (k + 1) * BK, nB, wv);
+                    da.issue(klo + (k + 1) * BK, nA, wv, lane);
+                    db.issue(klo + (k + 1) * BK, nB, wv, lane);
                 }
                 if (next_reg) {
                     oa.fetch(ra, klo + (k + 1) * BK, khi);
@@ -750,7 +680,7 @@ __device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn,
             }
         }
     }
-    epilogue<double>(P, acc, i0, j0, split, slot, tid);
+    epilogue<T>(P, acc, i0, j0, split, slot, tid);
 }
 
 // V selects a separately named instantiation: 1 for the smoother's N x N x N
@@ -761,9 +691,7 @@ __device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn,
 // layouts compiled in (bit L for layout L); each problem of the group picks its own.
 template <typename T, int V, int MASK>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmGroup G) {
-    __shared__ T As[2 * BK * BM];
-    __shared__ T Bs[2 * BK * BN];
-    __shared__ double Ad0[BK * BM], Ad1[BK * BM], Bd0[BK * BN], Bd1[BK * BN];
+    __shared__ T Ad0[BK * BM], Ad1[BK * BM], Bd0[BK * BN], Bd1[BK * BN];
     int q = 0;
 #pragma unroll
     for (int u = 1; u < kMaxGroup; ++u)
@@ -791,13 +719,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmGroup G) {
     const bool edge = P.M - bm * BM <= 48 || P.N - bn * BN <= 48;
 #define KF_T(ta, tb)                                                                    \
     do {                                                                                \
-        if constexpr (sizeof(T) == 8) {                                                 \
-            if (edge) fast_tile_dma<ta, tb, true>(P, bm, bn, split, slot, Ad0, Ad1, Bd0, Bd1); \
-            else fast_tile_dma<ta, tb, false>(P, bm, bn, split, slot, Ad0, Ad1, Bd0, Bd1);     \
-        } else {                                                                        \
-            if (edge) fast_tile<T, ta, tb, true>(P, bm, bn, split, slot, As, Bs);       \
-            else fast_tile<T, ta, tb, false>(P, bm, bn, split, slot, As, Bs);           \
-        }                                                                               \
+        if (edge) fast_tile_dma<T, ta, tb, true>(P, bm, bn, split, slot, Ad0, Ad1, Bd0, Bd1); \
+        else fast_tile_dma<T, ta, tb, false>(P, bm, bn, split, slot, Ad0, Ad1, Bd0, Bd1);     \
     } while (0)
     if ((MASK & 1) && lay == 0) KF_T(false, false);
     else if ((MASK & 2) && lay == 1) KF_T(true, false);
