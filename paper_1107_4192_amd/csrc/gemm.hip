@@ -5,11 +5,12 @@
 // sub-tile as 4 x 4 blocks of the 16x16x4 MFMA (f64 or f32), so every operand
 // fragment read from LDS feeds four MFMAs. Operand tiles of 16 k-steps are
 // staged through double-buffered LDS in a fixed [k][row] layout whatever the
-// global layout (transposing loads are done on the way in), with one barrier
-// per k-tile. Tiles go from global memory straight into LDS
-// (global_load_lds_dwordx4, one k-tile ahead), with no staging registers and no
-// LDS store instructions; a partial last k-tile, which must read zeros past K,
-// takes the register path.
+// global layout (transposing loads are done on the way in). Tiles go from global
+// memory straight into LDS (global_load_lds_dwordx4, one k-tile ahead), with no
+// staging registers and no LDS store instructions; the one barrier per k-tile sits
+// before its last k-step, so the next tile's first fragments are read from LDS while
+// that step's MFMAs run. A partial last k-tile, which must read zeros past K, takes
+// the register path after the others.
 //
 // Used for every dense product of the filter and smoother: X P_{t|t-1} and
 // X P X^T (eqn8), the rank-m downdate of the covariance update after eqn10,
@@ -600,7 +601,7 @@ __device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn,
         khi = min(khi, klo + chunk);
     }
     const int nk = khi > klo ? (khi - klo + BK - 1) / BK : 0;
-    const bool tail = ((khi - klo) & (BK - 1)) != 0;     // the last k-tile is partial
+    const bool tail = nk > 0 && ((khi - klo) & (BK - 1)) != 0;   // the last k-tile is partial
     constexpr bool RA = !TA, RB = TB;
 
     const int wave = tid >> 6, lane = tid & 63;
@@ -613,10 +614,6 @@ __device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn,
     DmaOp<T, RB> db;
     da.init(static_cast<const T*>(P.A), P.lda, P.M, i0, lane);
     db.init(static_cast<const T*>(P.B), P.ldb, P.N, j0, lane);
-    Operand<T, RA> oa;
-    Operand<T, RB> ob;
-    oa.init(static_cast<const T*>(P.A), P.lda, P.M, P.K, i0, tid);
-    ob.init(static_cast<const T*>(P.B), P.ldb, P.N, P.K, j0, tid);
 
     AV acc[4][4];
 #pragma unroll
@@ -646,39 +643,71 @@ __device__ __forceinline__ void fast_tile_dma(const GemmDesc& P, int bm, int bn,
                     if (!EDGE || (live >> (4 * a + b)) & 1u) acc[a][b] = Acc<T>::mfma(fa[a], fb[b], acc[a][b]);
         }
     };
-    if (nk > 0) {
-        if (nk == 1 && tail) {
-            T ra[8], rb[8];
-            oa.fetch(ra, klo, khi);
-            ob.fetch(rb, klo, khi);
-            put(As0, Bs0, ra, rb);
-        } else {
-            da.issue(klo, As0, wv, lane);
-            db.issue(klo, Bs0, wv, lane);
-        }
+    const int nfull = tail ? nk - 1 : nk;    // k-tiles loaded straight into LDS
+    if (nfull > 0) {
+        // One barrier per k-tile, between its third and fourth k-steps: by then tile k + 1 has
+        // landed (its loads were issued as tile k began) and every wave has read all of tile k
+        // (the fourth k-step's fragments are read before it), so after it the next tile's first
+        // fragments are read while the fourth k-step's MFMAs run.
+        auto frag = [&](const T* as, const T* bs, int kk, T (&fa)[4], T (&fb)[4]) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) fa[a] = rd(as, RA, kk + lk, wm + a * 16 + lr);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) fb[b] = rd(bs, RB, kk + lk, wn + b * 16 + lr);
+        };
+        auto mfmas = [&](const T (&fa)[4], const T (&fb)[4]) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (!EDGE || (live >> (4 * a + b)) & 1u) acc[a][b] = Acc<T>::mfma(fa[a], fb[b], acc[a][b]);
+        };
+        da.issue(klo, As0, wv, lane);
+        db.issue(klo, Bs0, wv, lane);
         __syncthreads();
-        for (int kt = 0; kt < nk; kt += 2) {
+        T fa0[4], fb0[4];
+        frag(As0, Bs0, 0, fa0, fb0);
+        for (int kt = 0; kt < nfull; kt += 2) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int k = kt + h;
-                if (k >= nk) break;
-                T* nA = h ? As0 : As1;
-                T* nB = h ? Bs0 : Bs1;
-                const bool next = k + 1 < nk, next_reg = next && k + 1 == nk - 1 && tail;
-                T ra[8], rb[8];
-                if (next && !next_reg) {
-                    da.issue(klo + (k + 1) * BK, nA, wv, lane);
-                    db.issue(klo + (k + 1) * BK, nB, wv, lane);
+                if (k >= nfull) break;
+                const T* as = h ? As1 : As0;
+                const T* bs = h ? Bs1 : Bs0;
+                T* na = h ? As0 : As1;
+                T* nb = h ? Bs0 : Bs1;
+                const bool next = k + 1 < nfull;
+                if (next) {
+                    da.issue(klo + (k + 1) * BK, na, wv, lane);
+                    db.issue(klo + (k + 1) * BK, nb, wv, lane);
                 }
-                if (next_reg) {
-                    oa.fetch(ra, klo + (k + 1) * BK, khi);
-                    ob.fetch(rb, klo + (k + 1) * BK, khi);
-                }
-                tile(h ? As1 : As0, h ? Bs1 : Bs0);
-                if (next_reg) put(nA, nB, ra, rb);
+                T fa1[4], fb1[4], fa2[4], fb2[4], fa3[4], fb3[4];
+                frag(as, bs, 4, fa1, fb1);
+                mfmas(fa0, fb0);
+                frag(as, bs, 8, fa2, fb2);
+                mfmas(fa1, fb1);
+                frag(as, bs, 12, fa3, fb3);
+                mfmas(fa2, fb2);
                 __syncthreads();
+                if (next) frag(na, nb, 0, fa0, fb0);
+                mfmas(fa3, fb3);
             }
         }
+    }
+    if (tail) {   // the partial last k-tile through registers (k >= khi read as zero)
+        Operand<T, RA> oa;
+        Operand<T, RB> ob;
+        oa.init(static_cast<const T*>(P.A), P.lda, P.M, P.K, i0, tid);
+        ob.init(static_cast<const T*>(P.B), P.ldb, P.N, P.K, j0, tid);
+        T ra[8], rb[8];
+        const int k0 = klo + nfull * BK;
+        oa.fetch(ra, k0, khi);
+        ob.fetch(rb, k0, khi);
+        T* sa = (nfull & 1) ? As1 : As0;   // last read by tile nfull - 2, before the previous barrier
+        T* sb = (nfull & 1) ? Bs1 : Bs0;
+        put(sa, sb, ra, rb);
+        __syncthreads();
+        tile(sa, sb);
     }
     epilogue<T>(P, acc, i0, j0, split, slot, tid);
 }
