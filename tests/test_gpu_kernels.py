@@ -26,6 +26,8 @@ CASES = [
     (306, 500, 500, 0), (129, 129, 200, F.G_TA), (200, 77, 129, F.G_TB), (257, 140, 65, F.G_TA | F.G_TB),
     (300, 300, 70, F.G_LOWER), (300, 300, 70, F.G_LOWER | F.G_MIRROR), (300, 300, 70, F.G_LOWER | F.G_MIRROR | F.G_TA),
     (306, 306, 5124, F.G_TB),
+    # lower outputs of 9 and 17 tile rows: groups of 8 tile rows, the last one partial
+    (1100, 1100, 40, F.G_LOWER | F.G_MIRROR), (2100, 2100, 20, F.G_LOWER | F.G_TB),
 ]
 
 
