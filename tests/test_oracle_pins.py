@@ -241,19 +241,20 @@ def test_p10_calibration_chi_square():
 
 
 # ---------------------------------------------------------------- Section 2.4 set-up
-def test_init_from_mne_matches_outer_product_sum():
-    rng = np.random.default_rng(81)
-    N, m, T = 9, 4, 12
-    X = rng.normal(size=(m, N)); C = 0.5 * np.eye(N); R = synth.random_spd(rng, m, 3.0, 0.1)
-    Y = rng.normal(size=(T, m))
-    x0, Q = oracle.init_from_mne(X, C, R, Y, reg=1e-3)
-    J = oracle.mne_solve(X, C, R, Y)
-    assert np.array_equal(x0, J[0])
-    d = [J[k] - J[k - 1] for k in range(1, T)]
-    dbar = sum(d) / len(d)
-    S = sum(np.outer(v - dbar, v - dbar) for v in d) / (len(d) - 1) + 1e-3 * np.eye(N)
-    assert rel(Q, S) < 1e-12
-    assert np.linalg.eigvalsh(Q).min() >= 1e-3 * (1 - 1e-9)
+def test_init_from_mne_closed_form():
+    # X = I, C = c I, R = r I: the MNE estimate of eqn5 is exactly c / (c + r) times the data.
+    # Data whose differences alternate a, b, a, b have mean (a + b) / 2 and centred differences
+    # +-(a - b) / 2, so their sample covariance (divisor: differences - 1 = 3) is
+    # (a - b)(a - b)^T / 3, scaled by (c / (c + r))^2, plus reg I.
+    c, r, reg = 2.0, 0.5, 1e-3
+    s = c / (c + r)
+    a, b = np.array([1.0, 0.0]), np.array([-1.0, 2.0])
+    y0 = np.array([0.5, -1.0])
+    Y = np.array([y0, y0 + a, y0 + a + b, y0 + 2 * a + b, y0 + 2 * a + 2 * b])
+    x0, Q = oracle.init_from_mne(np.eye(2), c * np.eye(2), r * np.eye(2), Y, reg=reg)
+    assert np.allclose(x0, s * y0, rtol=0, atol=1e-15)
+    expect = s * s * np.outer(a - b, a - b) / 3.0 + reg * np.eye(2)
+    assert np.allclose(Q, expect, rtol=0, atol=1e-14)
 
 
 def test_init_from_mne_recovers_random_walk_covariance():
