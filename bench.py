@@ -360,7 +360,8 @@ def run_assoc(p, t_rts, xs_ref, ds_ref):
     ex = float(np.linalg.norm(xs.cpu().numpy() - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
     ed = float((np.abs(ds.cpu().numpy() - dref).max(axis=1) / np.abs(dref).max(axis=1)).max())
     out["paper"] = {"rts_s": t_rts, "assoc_s": t_assoc, "speedup": t_rts / t_assoc,
-                    "eps_x_smooth_vs_rts_path": ex, "eps_diagP_smooth_vs_rts_path": ed}
+                    "eps_x_smooth_vs_rts_path": ex, "eps_diagP_smooth_vs_rts_path": ed,
+                    "alloc_gib": kfmeg.kf_smooth_assoc_bytes(p.N, p.T) / 2**30}
     log(f"assoc paper: rts {t_rts:.2f} s, assoc {t_assoc:.2f} s")
     return out
 

@@ -167,14 +167,21 @@ kf_status kf_smooth_means_batch(kf_plan* plan, int64_t B, double* x_smooth);
  * Needs a float64 plan (KF_EINVAL for mixed precision or a serving plan) whose
  * last kf_filter call ran one data set and stored every P_{t|t} in float64 (no
  * float32 store, no checkpointing; KF_ESTATE otherwise). Allocates T + 23
- * float64 N x N matrices (rows padded to 16 elements) for the call (KF_ENOMEM
- * if that fails) and
+ * float64 N x N matrices (rows padded to 16 elements) for the call,
+ * kf_smooth_assoc_bytes(N, T) bytes (KF_ENOMEM if that fails), and
  * overwrites the stored P_{t|t}: afterwards the plan needs a new kf_filter
  * call before any smoother call or kf_get_filtered_cov. KF_ENOTPD as for
  * kf_smooth.
  */
 kf_status kf_smooth_assoc(kf_plan* plan, double* x_smooth, double* Pdiag_smooth,
                           double* P_smooth);
+
+/*
+ * Device bytes kf_smooth_assoc allocates for one call on a plan of N sources after a
+ * kf_filter call over T steps (on top of the plan's own kf_plan_bytes), so that a
+ * caller can budget them; 0 for N <= 0 or T <= 0. Host arithmetic only.
+ */
+size_t kf_smooth_assoc_bytes(int64_t N, int64_t T);
 
 /*
  * kf_set_transition: use x_t = F x_{t-1} + w_t (eqn3) instead of the random

@@ -230,6 +230,14 @@ size_t store_bytes(int64_t N, int64_t ldN, int64_t T, bool s32, int stride) {
     return (size_t)slots_needed(T, stride) * (size_t)N * ldN * (s32 && stride == 1 ? 4 : 8);
 }
 
+// Device bytes kf_smooth_assoc allocates for one call over T steps: the T - 1 scan elements E_t,
+// the scratch of one launch group of combines with an E E' product and of one without (kMaxGroup
+// / 2 and kMaxGroup matrices), and two N-vectors.
+size_t assoc_bytes(int64_t N, int64_t ldN, int64_t T) {
+    const size_t mats = (size_t)std::max<int64_t>(T - 1, 0) + kMaxGroup / 2 + kMaxGroup;
+    return mats * (size_t)N * ldN * 8 + 2 * (size_t)N * 8;
+}
+
 // Tail splits of the back-recursion's M = A_t D (whole) and P_t + M A_t^T (lower) products.
 constexpr int kTailUnits = 2048;
 void tail_splits(int64_t N, TailSplit& ts_m, TailSplit& ts_low) {
@@ -677,6 +685,11 @@ size_t kf_plan_bytes(int64_t N, int64_t m, int64_t T, const kf_options* opt) {
     return workspace_bytes(N, m, o.precision == KF_MIXED, o.store_fp32, stride, kMaxBatch) +
            store_bytes(N, ldN, T, o.store_fp32, stride) + bck_bytes(N, m, T, stride) +
            (o.keep_gain_factors ? factor_bytes(N, m, T) : 0);
+}
+
+size_t kf_smooth_assoc_bytes(int64_t N, int64_t T) {
+    if (N <= 0 || T <= 0) return 0;
+    return assoc_bytes(N, round_up(N, 16), T);
 }
 
 }  // extern "C"
@@ -1426,7 +1439,7 @@ kf_status smooth_assoc_impl(kf_plan* p, double* xs, double* Pdiag, double* Pfull
     constexpr int GE = kMaxGroup / 2;            // combines per launch group with an E E' product
     constexpr int G = kMaxGroup;                 // combines per launch group without one
     const int64_t nE = T - 1;
-    const size_t need = ((size_t)nE + GE + G) * mat * 8 + 2 * (size_t)N * 8;
+    const size_t need = assoc_bytes(N, ld, T);
     void* block = nullptr;
     if (hipMalloc(&block, need) != hipSuccess) {
         (void)hipGetLastError();

@@ -26,7 +26,7 @@ EXPORTS = ("kf_default_options", "kf_create", "kf_filter", "kf_smooth", "kf_get_
            "kfs_create", "kfs_submit", "kfs_wait", "kfs_job_info", "kfs_get_stats", "kfs_last_error",
            "kfs_destroy", "kf_init_from_mne", "kf_filter_batch", "kf_smooth_batch", "kfd_gemm_tail", "kf_smooth_means",
            "kf_smooth_means_batch", "kfs_cancel",
-           "kf_set_transition", "kf_smooth_assoc", "mne_solve_noalloc", "kfd_spd_solve")
+           "kf_set_transition", "kf_smooth_assoc", "kf_smooth_assoc_bytes", "mne_solve_noalloc", "kfd_spd_solve")
 
 
 class KFError(RuntimeError):
@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_last_error.restype = ctypes.c_char_p
     lib.kf_plan_bytes.argtypes = [i64, i64, i64, ctypes.POINTER(kf_options)]
     lib.kf_plan_bytes.restype = ctypes.c_size_t
+    lib.kf_smooth_assoc_bytes.argtypes = [i64, i64]
+    lib.kf_smooth_assoc_bytes.restype = ctypes.c_size_t
     lib.kf_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.kf_set_profiling.restype = ctypes.c_int
     lib.kf_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -175,6 +177,11 @@ def options(precision: int = KF_FP64, store_fp32: bool = False, hbm_budget_bytes
 def kf_plan_bytes(N: int, m: int, T: int, opt: kf_options | None = None) -> int:
     lib = load_library()
     return int(lib.kf_plan_bytes(N, m, T, ctypes.byref(opt) if opt is not None else None))
+
+
+def kf_smooth_assoc_bytes(N: int, T: int) -> int:
+    """Device bytes kf_smooth_assoc allocates for one call after a filter run over T steps."""
+    return int(load_library().kf_smooth_assoc_bytes(N, T))
 
 
 def kf_create(N, m, T_max, X, Q, R, x0, P0, opt: kf_options | None = None, stream=None) -> int:

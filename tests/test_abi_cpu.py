@@ -46,6 +46,10 @@ def test_plan_bytes_host_logic():
     store64 = 200 * 5124 * 5136 * 8
     assert b64 > store64 and b32 < b64 and ck < b64
     assert kfmeg.kf_plan_bytes(0, 306, 200, None) == 0
+    # the associative smoother's per-call allocation: T - 1 scan elements plus 8 + 16 scratch
+    # matrices of N x 5136 float64, and two N-vectors
+    assert kfmeg.kf_smooth_assoc_bytes(5124, 200) == (199 + 24) * 5124 * 5136 * 8 + 2 * 5124 * 8
+    assert kfmeg.kf_smooth_assoc_bytes(0, 200) == 0 and kfmeg.kf_smooth_assoc_bytes(5124, 0) == 0
 
 
 def test_product_path_has_no_oracle_import():
