@@ -95,6 +95,24 @@ def test_gemm_triangular_operands(dtype, n, k, padded):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("K,ksplit", [(20, 4), (3, 3), (33, 6), (50, 8)])
+def test_gemm_split_slices_past_k(dtype, K, ksplit):
+    """Split-K slices are whole multiples of 16 in k, so the last slices can start past K
+    (K = 20 in 4 slices: [0, 16), [16, 20), then two empty ones). An empty slice must add
+    nothing, also where its (negative) span is not a multiple of 16."""
+    g = torch.Generator().manual_seed(K * 31 + ksplit)
+    M, N = 200, 140
+    A = torch.randn((M, K), generator=g, dtype=torch.float64)
+    B = torch.randn((N, K), generator=g, dtype=torch.float64)
+    Ad, Bd = A.to(dtype), B.to(dtype)
+    ref = Ad.double() @ Bd.double().T
+    for dev in (lambda X: X.cuda(), _padded):
+        C = F.kfd_gemm(dev(Ad), dev(Bd), M, N, K, F.G_TB, 1.0, 0.0, ksplit=ksplit).cpu()
+        tol = (1e-13 if dtype == torch.float64 else 2e-6) * K ** 0.5 * 4 + 1e-6
+        assert (C - ref).abs().max() <= tol * max(1.0, ref.abs().max())
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("flags", [0, F.G_TB, F.G_TA, F.G_TB | F.G_LOWER | F.G_MIRROR])
 @pytest.mark.parametrize("full,k", [(0, 2), (7, 3), (20, 4), (35, 2)])
 def test_gemm_tail_split(dtype, flags, full, k):
